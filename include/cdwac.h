@@ -1,0 +1,228 @@
+/*
+ * cdwac.h - C ABI of the MI355X (gfx950) CD-WAC core-level G0W0 library.
+ *
+ * Computes core quasiparticle energies from Kohn-Sham orbital energies and
+ * RI-V three-centre coefficients by contour deformation with the screened
+ * interaction analytically continued from the imaginary axis (CD-WAC),
+ * after Panades-Barrueta & Golze, JCTC 2023:
+ *
+ *   Pi_PQ(z)   = spin sum_ia O^ia_P O^ia_Q [1/(z - D_ia) - 1/(z + D_ia)]   Eq. (piriv)
+ *   Lambda(z)  = [I - Pi(z)]^-1 - I                                        Eq. (bigLambda)
+ *   W^c_nm(z)  = sum_PQ O^nm_P Lambda_PQ(z) O^mn_Q                         Eq. (wriv)
+ *   T_nm(z)    = greedy Thiele continued fraction in z^2                   Eqs. (pade, rec_eq), Sec. 3.2
+ *   Sigma_n(w) = Sigma^x_n + R_n(w) - I_n(w)                               Eqs. (In_term, Rn_term, cdselfe)
+ *   eps^QP_n   = eps_n + Re Sigma_n(eps^QP_n) - v^xc_n                     Eq. (qp_eq)
+ *
+ * Conventions
+ *   - Energies in Hartree.  Arrays are row-major (last index fastest).
+ *   - "host" pointers are read during the call only; "device" pointers are
+ *     HIP device memory on the context's device.  The caller owns every
+ *     buffer it passes; the library never frees caller memory.
+ *   - Every function returns a cdwac_status.  Arguments are validated before
+ *     any kernel is launched; on an error nothing is written to outputs and
+ *     cdwac_last_error() describes the problem.  Device-side failures (a
+ *     singular pivot in the dielectric inversion) are reported after the
+ *     call has synchronised its stream.
+ *   - All work is queued on the context's stream; every call returns after
+ *     that stream has been synchronised.  One context per host thread.
+ *   - Calls that overlap on one context are not allowed.
+ */
+#ifndef CDWAC_H
+#define CDWAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cdwac_ctx cdwac_ctx;
+
+typedef enum {
+    CDWAC_OK = 0,
+    CDWAC_EINVAL = -1,   /* invalid argument (shape, ordering, NaN, NULL)            */
+    CDWAC_ENOMEM = -2,   /* device allocation failed or caller workspace too small   */
+    CDWAC_EHIP = -3,     /* a HIP runtime call failed                                */
+    CDWAC_ENOTPD = -4,   /* zero or non-finite pivot while inverting eps = I - Pi    */
+    CDWAC_ESTATE = -5,   /* cdwac_qp / cdwac_sigma / cdwac_w_table before prepare    */
+    CDWAC_WNOROOT = 1    /* warning: at least one state has no root (qp = NaN)       */
+} cdwac_status;
+
+/* Arithmetic of the two dense contractions (Pi and W).  The dielectric
+ * inversion, the Pade recursion, the self-energy and the root search are
+ * always FP64. */
+typedef enum {
+    CDWAC_P64 = 0,       /* FP64 matrix cores                                        */
+    CDWAC_B16X3 = 1,     /* bf16 hi/lo split (16-bit significands), 3 products       */
+    CDWAC_B16 = 2,       /* plain bf16, one product (accuracy ablation only)         */
+    CDWAC_F16X3 = 3      /* fp16 hi/lo split of power-of-two-scaled operands (22-bit
+                            significands), 3 products; same matrix-core rate as bf16 */
+} cdwac_prec;
+/* Every 16-bit mode accumulates in FP32 and flushes the sums into FP64 every
+ * 2048 terms of the contraction. */
+
+/* Per-state outcome flags. */
+enum {
+    CDWAC_FLAG_NOROOT = 1,       /* no admissible root in the window: qp = NaN       */
+    CDWAC_FLAG_FALLBACK = 2,     /* secant failed, scan + bisection was used          */
+    CDWAC_FLAG_MLP_ACCEPTED = 4  /* learned seed accepted without further iteration   */
+};
+
+/* The molecule: mean-field energies and RI-V coefficients (Sec. 2.1-2.2). */
+typedef struct {
+    int32_t n_mo;              /* number of orbitals                                       */
+    int32_t n_occ;             /* occupied orbitals, 1 <= n_occ < n_mo                     */
+    int32_t n_aux;             /* auxiliary (RI) functions                                 */
+    int32_t n_states;          /* core states to solve, >= 1                               */
+    const int32_t *state_idx;  /* host [n_states]: orbital index of each state, < n_occ   */
+    const double *eps;         /* host [n_mo]: KS energies, strictly ascending             */
+    const double *vxc;         /* host [n_states]: <n|v_xc|n>; NULL means v^xc = Sigma^x   */
+    const double *o_ia;        /* device [n_aux][n_occ*(n_mo-n_occ)]: O^{ia}_P, a fastest  */
+    const double *o_nm;        /* device [n_states][n_aux][n_mo]: O^{nm}_P of each state   */
+    double spin;               /* spin factor of Pi; 2 for a closed shell                  */
+    double eps_fermi;          /* Fermi level; NaN selects (HOMO + LUMO) / 2               */
+} cdwac_system;
+
+/* Frequencies, Pade reference set and solver settings (Secs. 3.3, 3.4, 4). */
+typedef struct {
+    int32_t n_freq;            /* imaginary quadrature nodes, >= 1                         */
+    const double *freq;        /* host [n_freq]: omega_k > 0                               */
+    const double *weight;      /* host [n_freq]: quadrature weights for int_0^inf          */
+    int32_t n_ref_im;          /* imaginary nodes re-used as Pade references               */
+    const int32_t *ref_im_idx; /* host [n_ref_im]: distinct indices into freq              */
+    int32_t n_ref_re;          /* near-real Pade references x_j + i*eta_ref                */
+    const double *ref_re;      /* host [n_ref_re]: x_j >= 0                                */
+    double eta_ref;            /* imaginary part of the near-real references (> 0)         */
+    double eta;                /* broadening of the residue term, W(|eps_m - w| + i eta)   */
+    double pade_tol;           /* greedy stop: max remaining L1 error <= tol * max|W|      */
+    const double *win_lo;      /* host [n_states]: QP search window                        */
+    const double *win_hi;      /* host [n_states]                                          */
+    double qp_tol;             /* secant step tolerance (Ha), e.g. 1e-10                   */
+    int32_t qp_maxit;          /* secant iterations, e.g. 100                              */
+    int32_t prec;              /* cdwac_prec                                               */
+    int32_t use_mlp_seed;      /* 1: start the root search at the learned seed             */
+    double mlp_accept;         /* |f(seed)| (Ha) below which the seed is the answer        */
+} cdwac_params;
+
+/* Result for one state (host, written by cdwac_qp / cdwac_solve). */
+typedef struct {
+    double qp;                 /* quasiparticle energy, NaN if no root                     */
+    double z;                  /* renormalisation factor 1 / (1 - dSigma/dw) at qp         */
+    double sigma_x;            /* exchange self-energy Sigma^x_n                           */
+    double sigma_c;            /* Re Sigma^c_n(qp) = R_n(qp) - I_n(qp)                      */
+    double residual;           /* f(qp) = qp - eps_n - Re Sigma_n(qp) + v^xc_n             */
+    int32_t n_evals;           /* self-energy evaluations used                             */
+    int32_t flags;             /* CDWAC_FLAG_*                                             */
+} cdwac_state_out;
+
+/* Context: binds a device and a stream.  hip_stream NULL = the null stream. */
+int cdwac_ctx_create(cdwac_ctx **out, int device, void *hip_stream);
+void cdwac_ctx_destroy(cdwac_ctx *ctx);
+const char *cdwac_last_error(const cdwac_ctx *ctx);
+
+/* Device workspace needed by cdwac_prepare for this system and settings. */
+size_t cdwac_workspace_bytes(const cdwac_system *sys, const cdwac_params *prm);
+
+/* Hands the context a caller-owned device workspace (e.g. a torch tensor).
+ * Without one, cdwac_prepare allocates (and the context frees) its own. */
+int cdwac_set_workspace(cdwac_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Stages (a) Pi, (b) eps = I - Pi and Lambda, (c) W^c_nm at every imaginary
+ * node and near-real reference, Sigma^x, and (d) the greedy Thiele fits of
+ * every (n, m) whose residue can enter a window (Sec. 3.4, everything before
+ * the QP iteration).  The results stay in the workspace for the calls below;
+ * the input arrays may be freed afterwards. */
+int cdwac_prepare(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm);
+
+/* Stage (e): Sigma_n(omega) and the QP root for every state, using the
+ * prepared W tables and fits.  vxc: host [n_states] or NULL (the value given
+ * to prepare).  out: host [n_states]. */
+int cdwac_qp(cdwac_ctx *ctx, const double *vxc, cdwac_state_out *out);
+
+/* cdwac_prepare followed by cdwac_qp. */
+int cdwac_solve(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm,
+                cdwac_state_out *out);
+
+/* Re Sigma_n(omega) = Sigma^x + Re R_n - I_n (Eq. cdselfe) at n_omega
+ * frequencies per state.  omega, sigma: device [n_states][n_omega].
+ * Also writes I_n and R_n when i_term / r_term are non-NULL (same shape). */
+int cdwac_sigma(cdwac_ctx *ctx, int32_t n_omega, const double *omega, double *sigma,
+                double *i_term, double *r_term);
+
+/* Copies of the prepared tables (device outputs):
+ * w_im [n_states][n_mo][n_freq]  W^c_nm(i omega_k), real;
+ * w_re [n_fit][n_ref_re][2]      W^c_nm(x_j + i eta_ref) for the fitted (n, m),
+ *                                 in the order of cdwac_fit_ranges;
+ * sigma_x [n_states].  Any pointer may be NULL. */
+int cdwac_w_table(cdwac_ctx *ctx, double *w_im, double *w_re, double *sigma_x);
+
+/* Fitted orbital range [m0, m1) of each state (host [n_states] each). */
+int cdwac_fit_ranges(cdwac_ctx *ctx, int32_t *m0, int32_t *m1, int32_t *n_fit_total);
+
+/* Stage (a) alone: Pi(z) for n_z complex arguments z = z_re + i z_im (host).
+ * pi_re, pi_im: device [n_z][n_aux][n_aux], full symmetric; pi_im may be NULL
+ * when every z_re is 0 (Pi is then real). */
+int cdwac_polarizability(cdwac_ctx *ctx, const cdwac_system *sys, int32_t prec, int32_t n_z,
+                         const double *z_re, const double *z_im, double *pi_re, double *pi_im);
+
+/* Stage (d) alone: greedy Thiele fits of n_fit independent data sets and
+ * their values at n_x points each.  u, w: device [n_fit][n_pts][2] (complex
+ * u_j = z_j^2 and W_j); x: device [n_fit][n_x][2] (complex z^2 at which to
+ * evaluate); out: device [n_fit][n_x][2]; n_terms: device [n_fit] or NULL.
+ * n_pts <= 64. */
+int cdwac_pade_fit_eval(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const double *u,
+                        const double *w, double tol, int32_t n_x, const double *x,
+                        double *out, int32_t *n_terms);
+
+/* Per-stage timing with HIP events recorded on the context's stream around
+ * the kernels of each stage (0 = off, the default). */
+int cdwac_set_timing(cdwac_ctx *ctx, int on);
+
+/* Milliseconds of the stages of the last cdwac_prepare / cdwac_qp with timing
+ * on: [0] staging (weights, operand split), [1] polarizability kernel,
+ * [2] sweep inversion, [3] Lambda finalisation, [4] W contraction and
+ * reduction, [5] exchange and Pade fits, [6] QP kernel.  Writes min(n, 7)
+ * values; stages not run are 0. */
+#define CDWAC_N_STAGES 7
+int cdwac_get_timing(const cdwac_ctx *ctx, double *ms, int32_t n);
+
+/* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------
+ * Parameter vector (CDWAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64],
+ * b2[64], W3[1][64], b3[1].  Features of a state (Ha): eps_n, eps_F,
+ * Sigma^x - v^xc, Re Sigma^c at eps_n + {0, 1/8, 1/4, 3/8}, and the
+ * fixed-point guess Sigma^x - v^xc + Re Sigma^c(eps_n); the network predicts
+ * eps^QP - eps_n.  Inputs are standardised with (mu, sd) and the output is
+ * y * out_sd + out_mu. */
+#define CDWAC_MLP_NIN 8
+#define CDWAC_MLP_NPARAM 4801
+
+/* Installs the seed model used by cdwac_qp when use_mlp_seed = 1.
+ * theta: host [4801]; mu, sd: host [8]; out_mu, out_sd: scalars. */
+int cdwac_mlp_set_model(cdwac_ctx *ctx, const float *theta, const float *mu, const float *sd,
+                        float out_mu, float out_sd);
+
+/* Forward pass on n standardised samples: x device [n][8] -> y device [n]. */
+int cdwac_mlp_forward(cdwac_ctx *ctx, const float *theta, int32_t n, const float *x, float *y);
+
+/* Mean squared error loss and its gradient: x device [n][8], t device [n],
+ * grad device [4801], loss device [1]. */
+int cdwac_mlp_grad(cdwac_ctx *ctx, const float *theta, int32_t n, const float *x,
+                   const float *t, float *grad, float *loss);
+
+/* One Adam step (Kingma & Ba) in place on device theta, m, v [4801];
+ * step >= 1. */
+int cdwac_mlp_adam(cdwac_ctx *ctx, float *theta, const float *grad, float *m, float *v,
+                   int32_t step, float lr, float beta1, float beta2, float adam_eps);
+
+/* Minibatch training: epochs over n samples in a seeded shuffled order,
+ * batch size <= 1024.  theta, m, v: device [4801], updated in place;
+ * loss_curve: host [epochs] (mean loss per epoch) or NULL. */
+int cdwac_mlp_train(cdwac_ctx *ctx, float *theta, float *m, float *v, int32_t n,
+                    const float *x, const float *t, int32_t epochs, int32_t batch, float lr,
+                    uint64_t seed, float *loss_curve);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDWAC_H */

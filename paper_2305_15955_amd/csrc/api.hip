@@ -1,0 +1,965 @@
+// C ABI of the CD-WAC library: validation, workspace plan and stage order
+// (Sec. 3.4: wmatrix(F_im) -> wmatrix(F_real) -> AC -> QP iteration).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/cdwac.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace cdwac;
+
+namespace {
+
+// Fit ranges are widened by the Z-factor step of the root search so that
+// every self-energy evaluation of the solver finds a Pade model.
+constexpr double kFitMargin = 1e-4;
+
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+struct Plan {
+    // sizes
+    int n_mo, n_occ, n_virt, n_aux, S, n_freq, n_im, n_re, n_pts, n_f, prec;
+    int npad, cpad, cfpad, ni, n_fit, nblk;
+    int64_t K, kpad;
+    // persistent regions
+    Region eps, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
+        fit_m, w_im, w_re, coef, node, nterm, qpout, err;
+    // transient regions (prepare only)
+    Region zr, zi, part, idflag, amax, sf, cw, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
+        bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w;
+    size_t total = 0;
+};
+
+size_t add(Plan& p, Region& r, size_t bytes) {
+    r.off = p.total;
+    r.bytes = bytes;
+    p.total += (bytes + 255) / 256 * 256;
+    return r.off;
+}
+
+struct HostState {
+    std::vector<int> state_idx, m0, m1, fit_off, fit_s, fit_m;
+    std::vector<double> eps, vxc, win_lo, win_hi;
+    double eps_f = 0.0, eta = 0.0, qp_tol = 1e-10;
+    int qp_maxit = 100, use_mlp = 0;
+    double mlp_accept = 0.0;
+    bool vxc_is_sigx = false;
+};
+
+}  // namespace
+
+struct cdwac_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void* ws_user = nullptr;
+    size_t ws_user_bytes = 0;
+    void* ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    char* ws = nullptr;
+    bool prepared = false;
+    Plan plan{};
+    HostState hs;
+    // learned seed
+    float* mlp_theta = nullptr;
+    bool have_mlp = false;
+    float mlp_mu[8] = {}, mlp_sd[8] = {}, mlp_out_mu = 0.f, mlp_out_sd = 1.f;
+    // MLP scratch
+    void* mlp_scratch = nullptr;
+    size_t mlp_scratch_bytes = 0;
+    // stage timing: events ev[i] .. ev[i+1] bracket stage i of prepare; qp uses its own pair
+    bool timing = false;
+    hipEvent_t ev[CDWAC_N_STAGES + 1] = {};
+    hipEvent_t ev_qp[2] = {};
+    bool events_made = false;
+    double stage_ms[CDWAC_N_STAGES] = {};
+};
+
+namespace {
+
+int fail(cdwac_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCK(call)                                                                              \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, CDWAC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCK()                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = hipGetLastError();                                                          \
+        if (e_ != hipSuccess) return fail(ctx, CDWAC_EHIP, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_all(const double* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+int validate_system(cdwac_ctx* ctx, const cdwac_system* s) {
+    if (!s) return fail(ctx, CDWAC_EINVAL, "system is NULL");
+    if (s->n_mo < 2 || s->n_occ < 1 || s->n_occ >= s->n_mo)
+        return fail(ctx, CDWAC_EINVAL, "need 1 <= n_occ < n_mo (n_occ=%d, n_mo=%d)", s->n_occ, s->n_mo);
+    if (s->n_aux < 1) return fail(ctx, CDWAC_EINVAL, "n_aux must be >= 1");
+    if (s->n_states < 1) return fail(ctx, CDWAC_EINVAL, "n_states must be >= 1");
+    if (!s->state_idx || !s->eps || !s->o_ia || !s->o_nm) return fail(ctx, CDWAC_EINVAL, "NULL array in system");
+    if (!finite_all(s->eps, s->n_mo)) return fail(ctx, CDWAC_EINVAL, "non-finite orbital energy");
+    for (int m = 1; m < s->n_mo; ++m)
+        if (!(s->eps[m] > s->eps[m - 1]))
+            return fail(ctx, CDWAC_EINVAL, "orbital energies must be strictly ascending (index %d)", m);
+    for (int j = 0; j < s->n_states; ++j)
+        if (s->state_idx[j] < 0 || s->state_idx[j] >= s->n_mo)
+            return fail(ctx, CDWAC_EINVAL, "state_idx[%d] = %d out of range", j, s->state_idx[j]);
+    if (s->vxc && !finite_all(s->vxc, s->n_states)) return fail(ctx, CDWAC_EINVAL, "non-finite vxc");
+    if (!(s->spin > 0.0) || !std::isfinite(s->spin)) return fail(ctx, CDWAC_EINVAL, "spin factor must be > 0");
+    int64_t K = (int64_t)s->n_occ * (s->n_mo - s->n_occ);
+    if (K > (int64_t)1 << 31) return fail(ctx, CDWAC_EINVAL, "n_occ * n_virt too large");
+    return CDWAC_OK;
+}
+
+int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p) {
+    if (!p) return fail(ctx, CDWAC_EINVAL, "params is NULL");
+    if (p->n_freq < 1 || p->n_freq > qp_max_freq())
+        return fail(ctx, CDWAC_EINVAL, "n_freq must be in [1, %d]", qp_max_freq());
+    if (!p->freq || !p->weight) return fail(ctx, CDWAC_EINVAL, "NULL frequency grid");
+    for (int k = 0; k < p->n_freq; ++k)
+        if (!(p->freq[k] > 0.0) || !std::isfinite(p->freq[k]) || !std::isfinite(p->weight[k]))
+            return fail(ctx, CDWAC_EINVAL, "frequency node %d must be finite and > 0", k);
+    if (p->n_ref_im < 0 || p->n_ref_re < 0) return fail(ctx, CDWAC_EINVAL, "negative reference count");
+    if (p->n_ref_im + p->n_ref_re < 1 || p->n_ref_im + p->n_ref_re > kMaxPade)
+        return fail(ctx, CDWAC_EINVAL, "Pade reference count must be in [1, %d]", kMaxPade);
+    if (p->n_ref_im > 0 && !p->ref_im_idx) return fail(ctx, CDWAC_EINVAL, "ref_im_idx is NULL");
+    std::vector<char> seen(p->n_freq, 0);
+    for (int j = 0; j < p->n_ref_im; ++j) {
+        int k = p->ref_im_idx[j];
+        if (k < 0 || k >= p->n_freq || seen[k]) return fail(ctx, CDWAC_EINVAL, "ref_im_idx must be distinct grid indices");
+        seen[k] = 1;
+    }
+    if (p->n_ref_re > 0) {
+        if (!p->ref_re) return fail(ctx, CDWAC_EINVAL, "ref_re is NULL");
+        for (int j = 0; j < p->n_ref_re; ++j)
+            if (!(p->ref_re[j] >= 0.0) || !std::isfinite(p->ref_re[j]))
+                return fail(ctx, CDWAC_EINVAL, "ref_re[%d] must be finite and >= 0", j);
+        if (!(p->eta_ref > 0.0) || !std::isfinite(p->eta_ref)) return fail(ctx, CDWAC_EINVAL, "eta_ref must be > 0");
+    }
+    if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(ctx, CDWAC_EINVAL, "eta must be >= 0");
+    if (!(p->pade_tol >= 0.0)) return fail(ctx, CDWAC_EINVAL, "pade_tol must be >= 0");
+    if (!p->win_lo || !p->win_hi) return fail(ctx, CDWAC_EINVAL, "NULL QP window");
+    for (int j = 0; j < s->n_states; ++j)
+        if (!std::isfinite(p->win_lo[j]) || !std::isfinite(p->win_hi[j]) || !(p->win_lo[j] < p->win_hi[j]))
+            return fail(ctx, CDWAC_EINVAL, "QP window %d must satisfy lo < hi", j);
+    if (!(p->qp_tol > 0.0) || p->qp_maxit < 1) return fail(ctx, CDWAC_EINVAL, "qp_tol > 0 and qp_maxit >= 1 required");
+    if (p->prec < CDWAC_P64 || p->prec > CDWAC_F16X3) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", p->prec);
+    if (p->use_mlp_seed != 0 && p->use_mlp_seed != 1) return fail(ctx, CDWAC_EINVAL, "use_mlp_seed must be 0 or 1");
+    if (p->use_mlp_seed && !(p->mlp_accept >= 0.0)) return fail(ctx, CDWAC_EINVAL, "mlp_accept must be >= 0");
+    return CDWAC_OK;
+}
+
+// Orbitals whose residue can enter the window [lo, hi] (Eq. ffact):
+// occupied m with eps_m >= lo and virtual m with eps_m <= hi, a range [m0, m1).
+void fit_range(const double* eps, int n_mo, int n_occ, double lo, double hi, int& m0, int& m1) {
+    m0 = (int)(std::lower_bound(eps, eps + n_occ, lo) - eps);
+    m1 = n_occ + (int)(std::upper_bound(eps + n_occ, eps + n_mo, hi) - (eps + n_occ));
+}
+
+Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
+    Plan P{};
+    P.n_mo = s->n_mo;
+    P.n_occ = s->n_occ;
+    P.n_virt = s->n_mo - s->n_occ;
+    P.n_aux = s->n_aux;
+    P.S = s->n_states;
+    P.n_freq = p->n_freq;
+    P.n_im = p->n_ref_im;
+    P.n_re = p->n_ref_re;
+    P.n_pts = P.n_im + P.n_re;
+    P.n_f = P.n_freq + 2 * P.n_re;
+    P.prec = p->prec;
+    P.K = (int64_t)P.n_occ * P.n_virt;
+    P.kpad = round_up(P.K, 32);
+    P.npad = (int)round_up(P.n_aux, kPad);
+    P.nblk = P.npad / kNb;
+    P.cpad = (int)round_up((int64_t)P.S * P.n_mo, kPad);
+    P.ni = w_partial_blocks(P.prec, P.npad);
+    // fit list
+    std::vector<int> m0(P.S), m1(P.S), off(P.S), fs, fm;
+    for (int j = 0; j < P.S; ++j) {
+        fit_range(s->eps, P.n_mo, P.n_occ, p->win_lo[j] - kFitMargin, p->win_hi[j] + kFitMargin, m0[j], m1[j]);
+        off[j] = (int)fs.size();
+        for (int m = m0[j]; m < m1[j]; ++m) {
+            fs.push_back(j);
+            fm.push_back(m);
+        }
+    }
+    P.n_fit = (int)fs.size();
+    P.cfpad = (int)round_up(std::max(P.n_fit, 1), kPad);
+    if (hs) {
+        hs->m0 = m0;
+        hs->m1 = m1;
+        hs->fit_off = off;
+        hs->fit_s = fs;
+        hs->fit_m = fm;
+    }
+    const bool f64 = P.prec == CDWAC_P64;
+    const int64_t n2 = (int64_t)P.npad * P.npad;
+    const int64_t blk = (int64_t)kNb * kNb;
+    // persistent
+    add(P, P.eps, sizeof(double) * P.n_mo);
+    add(P, P.freq, sizeof(double) * P.n_freq);
+    add(P, P.weight, sizeof(double) * P.n_freq);
+    add(P, P.ref_re, sizeof(double) * std::max(P.n_re, 1));
+    add(P, P.ref_im, sizeof(int) * std::max(P.n_im, 1));
+    add(P, P.state_idx, sizeof(int) * P.S);
+    add(P, P.vxc, sizeof(double) * P.S);
+    add(P, P.sigx, sizeof(double) * P.S);
+    add(P, P.win_lo, sizeof(double) * P.S);
+    add(P, P.win_hi, sizeof(double) * P.S);
+    add(P, P.m0, sizeof(int) * P.S);
+    add(P, P.m1, sizeof(int) * P.S);
+    add(P, P.fit_off, sizeof(int) * P.S);
+    add(P, P.fit_s, sizeof(int) * std::max(P.n_fit, 1));
+    add(P, P.fit_m, sizeof(int) * std::max(P.n_fit, 1));
+    add(P, P.w_im, sizeof(double) * (size_t)P.S * P.n_mo * P.n_freq);
+    add(P, P.w_re, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * std::max(P.n_re, 1));
+    add(P, P.coef, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * P.n_pts);
+    add(P, P.node, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * P.n_pts);
+    add(P, P.nterm, sizeof(int) * std::max(P.n_fit, 1));
+    add(P, P.qpout, sizeof(QpOut) * P.S);
+    add(P, P.err, sizeof(int) * 4);
+    // transient
+    add(P, P.zr, sizeof(double) * P.n_f);
+    add(P, P.zi, sizeof(double) * P.n_f);
+    add(P, P.part, sizeof(int) * P.n_f);
+    add(P, P.idflag, sizeof(int) * P.n_f);
+    // operand maxima: [0] |O^ia|, [1] |O^nm|, [2..2+F) |c_f|, [2+F..2+2F) |Lambda_f|
+    add(P, P.amax, sizeof(uint32_t) * (2 + 2 * (size_t)P.n_f));
+    // scales: [0] x, [1] B, cfac[F], pi_unscale[F], lam_scale[F], w_unscale[F]
+    add(P, P.sf, sizeof(double) * (2 + 4 * (size_t)P.n_f));
+    add(P, P.cw, (f64 ? sizeof(double) : sizeof(float)) * (size_t)P.n_f * P.kpad);
+    if (f64) {
+        add(P, P.x64, sizeof(double) * (size_t)P.npad * P.kpad);
+    } else {
+        add(P, P.xh, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
+        add(P, P.xl, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
+    }
+    add(P, P.E, sizeof(double) * (size_t)P.n_f * n2);
+    add(P, P.dinv_r, sizeof(double) * (size_t)std::max(P.n_freq, 1) * blk);
+    add(P, P.pbuf_r, sizeof(double) * (size_t)P.n_freq * P.nblk * blk);
+    add(P, P.qbuf_r, sizeof(double) * (size_t)P.n_freq * P.nblk * blk);
+    add(P, P.dinv_c, sizeof(double) * 2 * (size_t)std::max(P.n_re, 1) * blk);
+    add(P, P.pbuf_c, sizeof(double) * 2 * (size_t)P.n_re * P.nblk * blk);
+    add(P, P.qbuf_c, sizeof(double) * 2 * (size_t)P.n_re * P.nblk * blk);
+    if (!f64) {
+        add(P, P.lh, sizeof(uint16_t) * (size_t)P.n_f * n2);
+        add(P, P.ll, sizeof(uint16_t) * (size_t)P.n_f * n2);
+    }
+    add(P, P.bt64, sizeof(double) * (size_t)P.cpad * P.npad);
+    add(P, P.bf64, sizeof(double) * (size_t)P.cfpad * P.npad);
+    if (!f64) {
+        add(P, P.bh, sizeof(uint16_t) * (size_t)P.cpad * P.npad);
+        add(P, P.bl, sizeof(uint16_t) * (size_t)P.cpad * P.npad);
+        add(P, P.bfh, sizeof(uint16_t) * (size_t)P.cfpad * P.npad);
+        add(P, P.bfl, sizeof(uint16_t) * (size_t)P.cfpad * P.npad);
+    }
+    add(P, P.partial_im, sizeof(double) * (size_t)P.n_freq * P.ni * P.cpad);
+    add(P, P.partial_re, sizeof(double) * 2 * (size_t)std::max(P.n_re, 1) * P.ni * P.cfpad);
+    add(P, P.rowsel, sizeof(int) * std::max(P.n_fit, 1));
+    add(P, P.ref_u, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * P.n_pts);
+    add(P, P.ref_w, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * P.n_pts);
+    return P;
+}
+
+template <typename T>
+T* at(cdwac_ctx* c, const Region& r) {
+    return reinterpret_cast<T*>(c->ws + r.off);
+}
+
+int ensure_workspace(cdwac_ctx* ctx, size_t bytes) {
+    if (ctx->ws_user) {
+        if (ctx->ws_user_bytes < bytes)
+            return fail(ctx, CDWAC_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ctx->ws_user_bytes,
+                        bytes);
+        ctx->ws = (char*)ctx->ws_user;
+        return CDWAC_OK;
+    }
+    if (ctx->ws_own_bytes < bytes) {
+        if (ctx->ws_own) {
+            HIPCK(hipStreamSynchronize(ctx->stream));
+            HIPCK(hipFree(ctx->ws_own));
+            ctx->ws_own = nullptr;
+            ctx->ws_own_bytes = 0;
+        }
+        if (hipMalloc(&ctx->ws_own, bytes) != hipSuccess) {
+            ctx->ws_own = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, CDWAC_ENOMEM, "cannot allocate %zu bytes of workspace", bytes);
+        }
+        ctx->ws_own_bytes = bytes;
+    }
+    ctx->ws = (char*)ctx->ws_own;
+    return CDWAC_OK;
+}
+
+template <typename T>
+int upload(cdwac_ctx* ctx, T* dst, const T* src, size_t n) {
+    if (n == 0) return CDWAC_OK;
+    HIPCK(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    return CDWAC_OK;
+}
+
+#define TRY(x)                       \
+    do {                             \
+        int r_ = (x);                \
+        if (r_ != CDWAC_OK) return r_; \
+    } while (0)
+
+int make_events(cdwac_ctx* ctx) {
+    if (ctx->events_made) return CDWAC_OK;
+    for (auto& e : ctx->ev) HIPCK(hipEventCreate(&e));
+    for (auto& e : ctx->ev_qp) HIPCK(hipEventCreate(&e));
+    ctx->events_made = true;
+    return CDWAC_OK;
+}
+
+// Records the boundary before stage i (i = CDWAC_N_STAGES - 1 closes the last prepare stage).
+int mark(cdwac_ctx* ctx, int i) {
+    if (!ctx->timing) return CDWAC_OK;
+    HIPCK(hipEventRecord(ctx->ev[i], ctx->stream));
+    return CDWAC_OK;
+}
+
+QpArgs qp_args(cdwac_ctx* c) {
+    const Plan& P = c->plan;
+    QpArgs a{};
+    a.n_mo = P.n_mo;
+    a.n_states = P.S;
+    a.n_freq = P.n_freq;
+    a.n_pts = P.n_pts;
+    a.eps = at<double>(c, P.eps);
+    a.freq = at<double>(c, P.freq);
+    a.weight = at<double>(c, P.weight);
+    a.w_im = at<double>(c, P.w_im);
+    a.coef = at<double>(c, P.coef);
+    a.node = at<double>(c, P.node);
+    a.nterm = at<int>(c, P.nterm);
+    a.fit_off = at<int>(c, P.fit_off);
+    a.m0 = at<int>(c, P.m0);
+    a.m1 = at<int>(c, P.m1);
+    a.state_idx = at<int>(c, P.state_idx);
+    a.sigx = at<double>(c, P.sigx);
+    a.vxc = at<double>(c, P.vxc);
+    a.win_lo = at<double>(c, P.win_lo);
+    a.win_hi = at<double>(c, P.win_hi);
+    a.eta = c->hs.eta;
+    a.eps_f = c->hs.eps_f;
+    a.qp_tol = c->hs.qp_tol;
+    a.qp_maxit = c->hs.qp_maxit;
+    a.use_mlp = c->hs.use_mlp;
+    a.mlp_accept = c->hs.mlp_accept;
+    a.mlp_theta = c->mlp_theta;
+    for (int i = 0; i < 8; ++i) {
+        a.mlp_mu[i] = c->mlp_mu[i];
+        a.mlp_sd[i] = c->mlp_sd[i];
+    }
+    a.mlp_out_mu = c->mlp_out_mu;
+    a.mlp_out_sd = c->mlp_out_sd;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdwac_ctx_create(cdwac_ctx** out, int device, void* hip_stream) {
+    if (!out) return CDWAC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CDWAC_EINVAL;
+    cdwac_ctx* ctx = new cdwac_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->mlp_theta, sizeof(float) * kMlpParams) != hipSuccess) {
+        delete ctx;
+        return CDWAC_EHIP;
+    }
+    *out = ctx;
+    return CDWAC_OK;
+}
+
+void cdwac_ctx_destroy(cdwac_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws_own) (void)hipFree(ctx->ws_own);
+    if (ctx->events_made) {
+        for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+        for (auto& e : ctx->ev_qp) (void)hipEventDestroy(e);
+    }
+    if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
+    if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
+    delete ctx;
+}
+
+const char* cdwac_last_error(const cdwac_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+size_t cdwac_workspace_bytes(const cdwac_system* sys, const cdwac_params* prm) {
+    if (validate_system(nullptr, sys) != CDWAC_OK || validate_params(nullptr, sys, prm) != CDWAC_OK) return 0;
+    return make_plan(sys, prm, nullptr).total;
+}
+
+int cdwac_set_workspace(cdwac_ctx* ctx, void* dev_ptr, size_t bytes) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (dev_ptr && ((uintptr_t)dev_ptr % 256) != 0) return fail(ctx, CDWAC_EINVAL, "workspace must be 256-byte aligned");
+    ctx->ws_user = dev_ptr;
+    ctx->ws_user_bytes = dev_ptr ? bytes : 0;
+    ctx->prepared = false;
+    return CDWAC_OK;
+}
+
+int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm) {
+    if (!ctx) return CDWAC_EINVAL;
+    ctx->prepared = false;
+    TRY(validate_system(ctx, sys));
+    TRY(validate_params(ctx, sys, prm));
+    if (prm->use_mlp_seed && !ctx->have_mlp) return fail(ctx, CDWAC_EINVAL, "use_mlp_seed set but no model installed");
+    HIPCK(hipSetDevice(ctx->device));
+    HostState hs;
+    Plan P = make_plan(sys, prm, &hs);
+    TRY(ensure_workspace(ctx, P.total));
+    ctx->plan = P;
+    hipStream_t st = ctx->stream;
+    const bool f64 = P.prec == CDWAC_P64;
+    const int64_t n2 = (int64_t)P.npad * P.npad;
+
+    // host state
+    hs.state_idx.assign(sys->state_idx, sys->state_idx + P.S);
+    hs.eps.assign(sys->eps, sys->eps + P.n_mo);
+    hs.win_lo.assign(prm->win_lo, prm->win_lo + P.S);
+    hs.win_hi.assign(prm->win_hi, prm->win_hi + P.S);
+    hs.eps_f = std::isnan(sys->eps_fermi) ? 0.5 * (sys->eps[P.n_occ - 1] + sys->eps[P.n_occ]) : sys->eps_fermi;
+    hs.eta = prm->eta;
+    hs.qp_tol = prm->qp_tol;
+    hs.qp_maxit = prm->qp_maxit;
+    hs.use_mlp = prm->use_mlp_seed;
+    hs.mlp_accept = prm->mlp_accept;
+    hs.vxc_is_sigx = sys->vxc == nullptr;
+    if (sys->vxc) hs.vxc.assign(sys->vxc, sys->vxc + P.S);
+
+    // weight vectors: imaginary nodes, then (Re, Im) of every near-real point
+    std::vector<double> zr(P.n_f), zi(P.n_f);
+    std::vector<int> part(P.n_f), idf(P.n_f);
+    for (int k = 0; k < P.n_freq; ++k) {
+        zr[k] = 0.0;
+        zi[k] = prm->freq[k];
+        part[k] = 0;
+        idf[k] = 1;
+    }
+    for (int j = 0; j < P.n_re; ++j)
+        for (int q = 0; q < 2; ++q) {
+            int f = P.n_freq + 2 * j + q;
+            zr[f] = prm->ref_re[j];
+            zi[f] = prm->eta_ref;
+            part[f] = q;
+            idf[f] = q == 0;
+        }
+    std::vector<int> rowsel(std::max(P.n_fit, 1), 0);
+    for (int f = 0; f < P.n_fit; ++f) rowsel[f] = hs.fit_s[f] * P.n_mo + hs.fit_m[f];
+
+    TRY(upload(ctx, at<double>(ctx, P.eps), sys->eps, P.n_mo));
+    TRY(upload(ctx, at<double>(ctx, P.freq), prm->freq, P.n_freq));
+    TRY(upload(ctx, at<double>(ctx, P.weight), prm->weight, P.n_freq));
+    if (P.n_re) TRY(upload(ctx, at<double>(ctx, P.ref_re), prm->ref_re, P.n_re));
+    if (P.n_im) TRY(upload(ctx, at<int>(ctx, P.ref_im), prm->ref_im_idx, P.n_im));
+    TRY(upload(ctx, at<int>(ctx, P.state_idx), sys->state_idx, P.S));
+    TRY(upload(ctx, at<double>(ctx, P.win_lo), prm->win_lo, P.S));
+    TRY(upload(ctx, at<double>(ctx, P.win_hi), prm->win_hi, P.S));
+    TRY(upload(ctx, at<int>(ctx, P.m0), hs.m0.data(), P.S));
+    TRY(upload(ctx, at<int>(ctx, P.m1), hs.m1.data(), P.S));
+    TRY(upload(ctx, at<int>(ctx, P.fit_off), hs.fit_off.data(), P.S));
+    if (P.n_fit) {
+        TRY(upload(ctx, at<int>(ctx, P.fit_s), hs.fit_s.data(), P.n_fit));
+        TRY(upload(ctx, at<int>(ctx, P.fit_m), hs.fit_m.data(), P.n_fit));
+    }
+    TRY(upload(ctx, at<int>(ctx, P.rowsel), rowsel.data(), rowsel.size()));
+    TRY(upload(ctx, at<double>(ctx, P.zr), zr.data(), P.n_f));
+    TRY(upload(ctx, at<double>(ctx, P.zi), zi.data(), P.n_f));
+    TRY(upload(ctx, at<int>(ctx, P.part), part.data(), P.n_f));
+    TRY(upload(ctx, at<int>(ctx, P.idflag), idf.data(), P.n_f));
+    int* err = at<int>(ctx, P.err);
+    HIPCK(hipMemsetAsync(err, 0, sizeof(int) * 4, st));
+    if (ctx->timing) TRY(make_events(ctx));
+    for (double& x : ctx->stage_ms) x = 0.0;
+
+    // (a0) staging: weights, operand maxima and scales, the O^{ia} operand
+    TRY(mark(ctx, 0));
+    const int et = prec_elem(P.prec);
+    uint32_t* amax = at<uint32_t>(ctx, P.amax);
+    double* sf = at<double>(ctx, P.sf);
+    double* pi_unscale = sf + 2 + P.n_f;
+    double* lam_scale = sf + 2 + 2 * P.n_f;
+    double* w_unscale = sf + 2 + 3 * P.n_f;
+    HIPCK(hipMemsetAsync(amax, 0, sizeof(uint32_t) * (2 + 2 * (size_t)P.n_f), st));
+    launch_absmax(st, sys->o_ia, P.K, P.n_aux, P.K, amax, err);
+    launch_absmax(st, sys->o_nm, P.n_mo, P.S * P.n_aux, P.n_mo, amax + 1, err);
+    launch_weights(st, at<double>(ctx, P.eps), P.n_occ, P.n_virt, sys->spin, at<double>(ctx, P.zr),
+                   at<double>(ctx, P.zi), at<int>(ctx, P.part), P.n_f, P.kpad,
+                   f64 ? at<double>(ctx, P.cw) : nullptr, f64 ? nullptr : at<float>(ctx, P.cw), amax + 2);
+    LAUNCHCK();
+    if (f64) {
+        launch_split_pad(st, 0, sys->o_ia, P.K, P.n_aux, P.K, nullptr, nullptr, nullptr, at<double>(ctx, P.x64),
+                         P.npad, P.kpad);
+    } else {
+        launch_scales_pi(st, amax, P.n_f, sf);
+        launch_scale_weights(st, at<float>(ctx, P.cw), P.kpad, P.n_f, sf + 2);
+        launch_split_pad(st, et, sys->o_ia, P.K, P.n_aux, P.K, sf, at<uint16_t>(ctx, P.xh), at<uint16_t>(ctx, P.xl),
+                         nullptr, P.npad, P.kpad);
+    }
+    LAUNCHCK();
+    // (a1) eps_f = I - Pi_f for every weight vector
+    TRY(mark(ctx, 1));
+    launch_pi(st, P.prec, P.npad, P.kpad, P.n_f, f64 ? at<double>(ctx, P.x64) : nullptr,
+              f64 ? nullptr : at<uint16_t>(ctx, P.xh), f64 ? nullptr : at<uint16_t>(ctx, P.xl),
+              f64 ? at<double>(ctx, P.cw) : nullptr, f64 ? nullptr : at<float>(ctx, P.cw), pi_unscale,
+              at<int>(ctx, P.idflag), at<double>(ctx, P.E));
+    LAUNCHCK();
+    // (a2) eps^-1 by blocked sweeps, Lambda = eps^-1 - I
+    TRY(mark(ctx, 2));
+    launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_freq, P.n_re, P.n_freq, at<double>(ctx, P.dinv_r),
+                 at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
+                 at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
+    LAUNCHCK();
+    TRY(mark(ctx, 3));
+    launch_finalize_lambda(st, at<double>(ctx, P.E), P.npad, P.n_f, at<int>(ctx, P.idflag),
+                           f64 ? nullptr : amax + 2 + P.n_f);
+    LAUNCHCK();
+    if (!f64) {
+        launch_scales_w(st, amax + 2 + P.n_f, P.n_f, sf, lam_scale, w_unscale);
+        launch_split_lambda(st, et, at<double>(ctx, P.E), P.npad, P.n_f, lam_scale, at<uint16_t>(ctx, P.lh),
+                            at<uint16_t>(ctx, P.ll));
+        LAUNCHCK();
+    }
+    // (a3) W^c_nm: all (n, m) at the imaginary nodes, fitted (n, m) at the near-real points
+    TRY(mark(ctx, 4));
+    const double* bscale = f64 ? nullptr : sf + 1;
+    launch_transpose_b(st, et, sys->o_nm, P.S, P.n_aux, P.n_mo, nullptr, P.S * P.n_mo, bscale, at<double>(ctx, P.bt64),
+                       f64 ? nullptr : at<uint16_t>(ctx, P.bh), f64 ? nullptr : at<uint16_t>(ctx, P.bl), P.cpad,
+                       P.npad, nullptr, err);
+    LAUNCHCK();
+    if (P.n_re > 0 && P.n_fit > 0) {
+        launch_transpose_b(st, et, sys->o_nm, P.S, P.n_aux, P.n_mo, at<int>(ctx, P.rowsel), P.n_fit, bscale,
+                           at<double>(ctx, P.bf64), f64 ? nullptr : at<uint16_t>(ctx, P.bfh),
+                           f64 ? nullptr : at<uint16_t>(ctx, P.bfl), P.cfpad, P.npad, nullptr, err);
+        LAUNCHCK();
+    }
+    launch_w(st, P.prec, P.npad, 0, P.n_freq, at<double>(ctx, P.E), f64 ? nullptr : at<uint16_t>(ctx, P.lh),
+             f64 ? nullptr : at<uint16_t>(ctx, P.ll), at<double>(ctx, P.bt64), f64 ? nullptr : at<uint16_t>(ctx, P.bh),
+             f64 ? nullptr : at<uint16_t>(ctx, P.bl), P.cpad, w_unscale, at<double>(ctx, P.partial_im));
+    LAUNCHCK();
+    if (P.n_re > 0 && P.n_fit > 0) {
+        launch_w(st, P.prec, P.npad, P.n_freq, 2 * P.n_re, at<double>(ctx, P.E),
+                 f64 ? nullptr : at<uint16_t>(ctx, P.lh), f64 ? nullptr : at<uint16_t>(ctx, P.ll),
+                 at<double>(ctx, P.bf64), f64 ? nullptr : at<uint16_t>(ctx, P.bfh),
+                 f64 ? nullptr : at<uint16_t>(ctx, P.bfl), P.cfpad, w_unscale, at<double>(ctx, P.partial_re));
+        LAUNCHCK();
+    }
+    launch_reduce_w(st, at<double>(ctx, P.partial_im), at<double>(ctx, P.partial_re), P.ni, P.cpad, P.cfpad,
+                    P.n_freq, P.n_re, P.S * P.n_mo, P.n_re > 0 ? P.n_fit : 0, at<double>(ctx, P.w_im),
+                    at<double>(ctx, P.w_re));
+    LAUNCHCK();
+    // (a4) Sigma^x and v^xc
+    TRY(mark(ctx, 5));
+    launch_exchange(st, sys->o_nm, P.S, P.n_aux, P.n_mo, P.n_occ, at<double>(ctx, P.sigx));
+    LAUNCHCK();
+    if (sys->vxc) TRY(upload(ctx, at<double>(ctx, P.vxc), sys->vxc, P.S));
+    else HIPCK(hipMemcpyAsync(at<double>(ctx, P.vxc), at<double>(ctx, P.sigx), sizeof(double) * P.S,
+                              hipMemcpyDeviceToDevice, st));
+    // (a5) greedy Thiele fits over F_wac
+    if (P.n_fit > 0) {
+        launch_gather_refs(st, P.n_fit, at<int>(ctx, P.fit_s), at<int>(ctx, P.fit_m), P.n_mo, P.n_freq,
+                           at<double>(ctx, P.w_im), at<double>(ctx, P.w_re), at<double>(ctx, P.freq),
+                           at<int>(ctx, P.ref_im), P.n_im, at<double>(ctx, P.ref_re), P.n_re, prm->eta_ref,
+                           at<double>(ctx, P.ref_u), at<double>(ctx, P.ref_w));
+        LAUNCHCK();
+        launch_thiele_fit(st, P.n_fit, P.n_pts, at<double>(ctx, P.ref_u), at<double>(ctx, P.ref_w), prm->pade_tol,
+                          at<double>(ctx, P.coef), at<double>(ctx, P.node), at<int>(ctx, P.nterm));
+        LAUNCHCK();
+    }
+    TRY(mark(ctx, 6));
+    int herr[4] = {0, 0, 0, 0};
+    HIPCK(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (ctx->timing) {
+        for (int i = 0; i < 6; ++i) {
+            float ms = 0.f;
+            HIPCK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+            ctx->stage_ms[i] = ms;
+        }
+    }
+    if (herr[0] & 2) return fail(ctx, CDWAC_EINVAL, "non-finite value in the RI coefficients");
+    if (herr[0] & 1) return fail(ctx, CDWAC_ENOTPD, "zero or non-finite pivot while inverting eps = I - Pi");
+    ctx->hs = hs;
+    ctx->prepared = true;
+    return CDWAC_OK;
+}
+
+int cdwac_qp(cdwac_ctx* ctx, const double* vxc, cdwac_state_out* out) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_qp called before cdwac_prepare");
+    if (!out) return fail(ctx, CDWAC_EINVAL, "out is NULL");
+    const Plan& P = ctx->plan;
+    if (vxc && !finite_all(vxc, P.S)) return fail(ctx, CDWAC_EINVAL, "non-finite vxc");
+    if (ctx->hs.use_mlp && !ctx->have_mlp) return fail(ctx, CDWAC_EINVAL, "no MLP model installed");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (vxc) TRY(upload(ctx, at<double>(ctx, P.vxc), vxc, P.S));
+    QpArgs a = qp_args(ctx);
+    if (ctx->timing) {
+        TRY(make_events(ctx));
+        HIPCK(hipEventRecord(ctx->ev_qp[0], st));
+    }
+    launch_qp(st, a, at<QpOut>(ctx, P.qpout));
+    LAUNCHCK();
+    if (ctx->timing) HIPCK(hipEventRecord(ctx->ev_qp[1], st));
+    static_assert(sizeof(QpOut) == sizeof(cdwac_state_out), "output layout");
+    HIPCK(hipMemcpyAsync(out, at<QpOut>(ctx, P.qpout), sizeof(QpOut) * P.S, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (ctx->timing) {
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, ctx->ev_qp[0], ctx->ev_qp[1]));
+        ctx->stage_ms[6] = ms;
+    }
+    for (int j = 0; j < P.S; ++j)
+        if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
+    return CDWAC_OK;
+}
+
+int cdwac_solve(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, cdwac_state_out* out) {
+    if (!out) return fail(ctx, CDWAC_EINVAL, "out is NULL");
+    TRY(cdwac_prepare(ctx, sys, prm));
+    return cdwac_qp(ctx, nullptr, out);
+}
+
+int cdwac_sigma(cdwac_ctx* ctx, int32_t n_omega, const double* omega, double* sigma, double* i_term,
+                double* r_term) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_sigma called before cdwac_prepare");
+    if (n_omega < 0 || (n_omega > 0 && (!omega || !sigma))) return fail(ctx, CDWAC_EINVAL, "bad omega/sigma");
+    if (n_omega > 65535) return fail(ctx, CDWAC_EINVAL, "n_omega must be <= 65535");
+    HIPCK(hipSetDevice(ctx->device));
+    QpArgs a = qp_args(ctx);
+    launch_sigma(ctx->stream, a, n_omega, omega, sigma, i_term, r_term);
+    LAUNCHCK();
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return CDWAC_OK;
+}
+
+int cdwac_w_table(cdwac_ctx* ctx, double* w_im, double* w_re, double* sigma_x) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_w_table called before cdwac_prepare");
+    const Plan& P = ctx->plan;
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (w_im)
+        HIPCK(hipMemcpyAsync(w_im, at<double>(ctx, P.w_im), sizeof(double) * (size_t)P.S * P.n_mo * P.n_freq,
+                             hipMemcpyDeviceToDevice, st));
+    if (w_re && P.n_re > 0 && P.n_fit > 0)
+        HIPCK(hipMemcpyAsync(w_re, at<double>(ctx, P.w_re), sizeof(double) * 2 * (size_t)P.n_fit * P.n_re,
+                             hipMemcpyDeviceToDevice, st));
+    if (sigma_x)
+        HIPCK(hipMemcpyAsync(sigma_x, at<double>(ctx, P.sigx), sizeof(double) * P.S, hipMemcpyDeviceToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+    return CDWAC_OK;
+}
+
+int cdwac_fit_ranges(cdwac_ctx* ctx, int32_t* m0, int32_t* m1, int32_t* n_fit_total) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_fit_ranges called before cdwac_prepare");
+    for (int j = 0; j < ctx->plan.S; ++j) {
+        if (m0) m0[j] = ctx->hs.m0[j];
+        if (m1) m1[j] = ctx->hs.m1[j];
+    }
+    if (n_fit_total) *n_fit_total = ctx->plan.n_fit;
+    return CDWAC_OK;
+}
+
+int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, int32_t n_z, const double* z_re,
+                         const double* z_im, double* pi_re, double* pi_im) {
+    if (!ctx) return CDWAC_EINVAL;
+    TRY(validate_system(ctx, sys));
+    if (prec < CDWAC_P64 || prec > CDWAC_F16X3) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", prec);
+    if (n_z < 1 || !z_re || !z_im || !pi_re) return fail(ctx, CDWAC_EINVAL, "bad z list or output");
+    bool all_imag = true;
+    for (int j = 0; j < n_z; ++j) {
+        if (!std::isfinite(z_re[j]) || !std::isfinite(z_im[j])) return fail(ctx, CDWAC_EINVAL, "non-finite z");
+        if (z_re[j] != 0.0) all_imag = false;
+    }
+    if (!all_imag && !pi_im) return fail(ctx, CDWAC_EINVAL, "pi_im required for z off the imaginary axis");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int n_virt = sys->n_mo - sys->n_occ;
+    const int64_t K = (int64_t)sys->n_occ * n_virt, kpad = round_up(K, 32);
+    const int npad = (int)round_up(sys->n_aux, kPad);
+    const int nf = 2 * n_z;
+    const bool f64 = prec == CDWAC_P64;
+    std::vector<double> zr(nf), zi(nf);
+    std::vector<int> part(nf), idf(nf, 0);
+    for (int j = 0; j < n_z; ++j)
+        for (int q = 0; q < 2; ++q) {
+            zr[2 * j + q] = z_re[j];
+            zi[2 * j + q] = z_im[j];
+            part[2 * j + q] = q;
+        }
+    size_t bytes = 0;
+    auto take = [&](size_t b) {
+        size_t o = bytes;
+        bytes += (b + 255) / 256 * 256;
+        return o;
+    };
+    size_t o_eps = take(sizeof(double) * sys->n_mo), o_zr = take(sizeof(double) * nf), o_zi = take(sizeof(double) * nf),
+           o_part = take(sizeof(int) * nf), o_id = take(sizeof(int) * nf), o_err = take(sizeof(int) * 4),
+           o_amax = take(sizeof(uint32_t) * (2 + 2 * (size_t)nf)), o_sf = take(sizeof(double) * (2 + 4 * (size_t)nf)),
+           o_cw = take((f64 ? 8 : 4) * (size_t)nf * kpad), o_x = take((f64 ? 8 : 4) * (size_t)npad * kpad),
+           o_E = take(sizeof(double) * (size_t)nf * npad * npad);
+    char* buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, CDWAC_ENOMEM, "cannot allocate %zu bytes", bytes);
+    }
+    int rc = CDWAC_OK;
+    do {
+        if (hipMemcpyAsync(buf + o_eps, sys->eps, sizeof(double) * sys->n_mo, hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(buf + o_zr, zr.data(), sizeof(double) * nf, hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(buf + o_zi, zi.data(), sizeof(double) * nf, hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(buf + o_part, part.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(buf + o_id, idf.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st) ||
+            hipMemsetAsync(buf + o_err, 0, sizeof(int) * 4, st) ||
+            hipMemsetAsync(buf + o_amax, 0, sizeof(uint32_t) * (2 + 2 * (size_t)nf), st)) {
+            rc = fail(ctx, CDWAC_EHIP, "upload failed");
+            break;
+        }
+        int* err = (int*)(buf + o_err);
+        uint32_t* amax = (uint32_t*)(buf + o_amax);
+        double* sf = (double*)(buf + o_sf);
+        launch_absmax(st, sys->o_ia, K, sys->n_aux, K, amax, err);
+        launch_weights(st, (double*)(buf + o_eps), sys->n_occ, n_virt, sys->spin, (double*)(buf + o_zr),
+                       (double*)(buf + o_zi), (int*)(buf + o_part), nf, kpad, f64 ? (double*)(buf + o_cw) : nullptr,
+                       f64 ? nullptr : (float*)(buf + o_cw), amax + 2);
+        uint16_t* xh = (uint16_t*)(buf + o_x);
+        uint16_t* xl = xh + (size_t)npad * kpad;
+        if (f64) {
+            launch_split_pad(st, 0, sys->o_ia, K, sys->n_aux, K, nullptr, nullptr, nullptr, (double*)(buf + o_x), npad,
+                             kpad);
+        } else {
+            launch_scales_pi(st, amax, nf, sf);
+            launch_scale_weights(st, (float*)(buf + o_cw), kpad, nf, sf + 2);
+            launch_split_pad(st, prec_elem(prec), sys->o_ia, K, sys->n_aux, K, sf, xh, xl, nullptr, npad, kpad);
+        }
+        launch_pi(st, prec, npad, kpad, nf, f64 ? (double*)(buf + o_x) : nullptr, f64 ? nullptr : xh,
+                  f64 ? nullptr : xl, f64 ? (double*)(buf + o_cw) : nullptr, f64 ? nullptr : (float*)(buf + o_cw),
+                  sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));
+        if (hipGetLastError() != hipSuccess) {
+            rc = fail(ctx, CDWAC_EHIP, "kernel launch failed");
+            break;
+        }
+        // E holds -Pi on the lower tiles; mirror to full symmetric outputs
+        const double* E = (const double*)(buf + o_E);
+        launch_extract_pi(st, E, npad, sys->n_aux, n_z, 0, pi_re);
+        if (pi_im) launch_extract_pi(st, E, npad, sys->n_aux, n_z, 1, pi_im);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(ctx, CDWAC_EHIP, "extract failed");
+            break;
+        }
+        int herr = 0;
+        if (rc == CDWAC_OK && (hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess))
+            rc = fail(ctx, CDWAC_EHIP, "copy failed");
+        if (rc == CDWAC_OK && (herr & 2)) rc = fail(ctx, CDWAC_EINVAL, "non-finite value in the RI coefficients");
+    } while (false);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    return rc;
+}
+
+int cdwac_pade_fit_eval(cdwac_ctx* ctx, int32_t n_fit, int32_t n_pts, const double* u, const double* w, double tol,
+                        int32_t n_x, const double* x, double* out, int32_t* n_terms) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (n_fit < 0 || n_pts < 1 || n_pts > kMaxPade || n_x < 0 || !(tol >= 0.0))
+        return fail(ctx, CDWAC_EINVAL, "bad fit sizes (n_pts must be in [1, %d])", kMaxPade);
+    if (n_fit == 0) return CDWAC_OK;
+    if (!u || !w || (n_x > 0 && (!x || !out))) return fail(ctx, CDWAC_EINVAL, "NULL array");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    size_t cb = sizeof(double) * 2 * (size_t)n_fit * n_pts;
+    char* buf = nullptr;
+    if (hipMalloc(&buf, 2 * cb + sizeof(int) * (size_t)n_fit + 512) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, CDWAC_ENOMEM, "cannot allocate fit buffers");
+    }
+    double* coef = (double*)buf;
+    double* node = (double*)(buf + cb);
+    int* nt = (int*)(buf + 2 * cb);
+    launch_thiele_fit(st, n_fit, n_pts, u, w, tol, coef, node, nt);
+    launch_thiele_eval(st, n_fit, n_pts, coef, node, nt, n_x, x, out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && n_terms) e = hipMemcpyAsync(n_terms, nt, sizeof(int) * n_fit, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(ctx, CDWAC_EHIP, "pade fit: %s", hipGetErrorString(e));
+    return CDWAC_OK;
+}
+
+int cdwac_set_timing(cdwac_ctx* ctx, int on) {
+    if (!ctx) return CDWAC_EINVAL;
+    ctx->timing = on != 0;
+    return CDWAC_OK;
+}
+
+int cdwac_get_timing(const cdwac_ctx* ctx, double* ms, int32_t n) {
+    if (!ctx || !ms || n < 0) return CDWAC_EINVAL;
+    for (int i = 0; i < n && i < CDWAC_N_STAGES; ++i) ms[i] = ctx->stage_ms[i];
+    return CDWAC_OK;
+}
+
+int cdwac_mlp_set_model(cdwac_ctx* ctx, const float* theta, const float* mu, const float* sd, float out_mu,
+                        float out_sd) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!theta || !mu || !sd) return fail(ctx, CDWAC_EINVAL, "NULL model array");
+    for (int i = 0; i < 8; ++i)
+        if (!(sd[i] > 0.f) || !std::isfinite(mu[i])) return fail(ctx, CDWAC_EINVAL, "feature scale must be > 0");
+    if (!(out_sd > 0.f)) return fail(ctx, CDWAC_EINVAL, "out_sd must be > 0");
+    HIPCK(hipSetDevice(ctx->device));
+    HIPCK(hipMemcpy(ctx->mlp_theta, theta, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
+    memcpy(ctx->mlp_mu, mu, sizeof ctx->mlp_mu);
+    memcpy(ctx->mlp_sd, sd, sizeof ctx->mlp_sd);
+    ctx->mlp_out_mu = out_mu;
+    ctx->mlp_out_sd = out_sd;
+    ctx->have_mlp = true;
+    return CDWAC_OK;
+}
+
+int cdwac_mlp_forward(cdwac_ctx* ctx, const float* theta, int32_t n, const float* x, float* y) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (n < 0 || (n > 0 && (!theta || !x || !y))) return fail(ctx, CDWAC_EINVAL, "bad MLP forward arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    launch_mlp_forward(ctx->stream, theta, n, x, y);
+    LAUNCHCK();
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return CDWAC_OK;
+}
+
+namespace {
+int mlp_scratch(cdwac_ctx* ctx, size_t bytes, char** out) {
+    if (ctx->mlp_scratch_bytes < bytes) {
+        if (ctx->mlp_scratch) {
+            HIPCK(hipStreamSynchronize(ctx->stream));
+            HIPCK(hipFree(ctx->mlp_scratch));
+            ctx->mlp_scratch = nullptr;
+            ctx->mlp_scratch_bytes = 0;
+        }
+        if (hipMalloc(&ctx->mlp_scratch, bytes) != hipSuccess) {
+            ctx->mlp_scratch = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, CDWAC_ENOMEM, "cannot allocate MLP scratch");
+        }
+        ctx->mlp_scratch_bytes = bytes;
+    }
+    *out = (char*)ctx->mlp_scratch;
+    return CDWAC_OK;
+}
+}  // namespace
+
+int cdwac_mlp_grad(cdwac_ctx* ctx, const float* theta, int32_t n, const float* x, const float* t, float* grad,
+                   float* loss) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (n < 1 || !theta || !x || !t || !grad || !loss) return fail(ctx, CDWAC_EINVAL, "bad MLP grad arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    int nb = mlp_grad_blocks(n);
+    char* s = nullptr;
+    TRY(mlp_scratch(ctx, sizeof(float) * ((size_t)nb * kMlpParams + nb) + 256, &s));
+    launch_mlp_grad(ctx->stream, theta, n, x, t, (float*)s, (float*)s + (size_t)nb * kMlpParams, grad, loss);
+    LAUNCHCK();
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return CDWAC_OK;
+}
+
+int cdwac_mlp_adam(cdwac_ctx* ctx, float* theta, const float* grad, float* m, float* v, int32_t step, float lr,
+                   float beta1, float beta2, float adam_eps) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!theta || !grad || !m || !v || step < 1) return fail(ctx, CDWAC_EINVAL, "bad Adam arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    launch_mlp_adam(ctx->stream, theta, grad, m, v, step, lr, beta1, beta2, adam_eps);
+    LAUNCHCK();
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return CDWAC_OK;
+}
+
+int cdwac_mlp_train(cdwac_ctx* ctx, float* theta, float* m, float* v, int32_t n, const float* x, const float* t,
+                    int32_t epochs, int32_t batch, float lr, uint64_t seed, float* loss_curve) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (n < 1 || epochs < 1 || batch < 1 || batch > 1024 || !theta || !m || !v || !x || !t)
+        return fail(ctx, CDWAC_EINVAL, "bad MLP train arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int nb = mlp_grad_blocks(batch);
+    const int nbatch = (n + batch - 1) / batch;
+    size_t o_part = 0, o_lp = o_part + sizeof(float) * (size_t)nb * kMlpParams;
+    size_t o_grad = round_up(o_lp + sizeof(float) * nb, 256);
+    size_t o_loss = round_up(o_grad + sizeof(float) * kMlpParams, 256);
+    size_t o_xb = round_up(o_loss + sizeof(float) * (size_t)nbatch, 256);
+    size_t o_tb = round_up(o_xb + sizeof(float) * 8 * (size_t)batch, 256);
+    size_t o_perm = round_up(o_tb + sizeof(float) * (size_t)batch, 256);
+    size_t total = round_up(o_perm + sizeof(int) * (size_t)n, 256);
+    char* s = nullptr;
+    TRY(mlp_scratch(ctx, total, &s));
+    std::vector<int> perm(n);
+    std::vector<float> losses(nbatch);
+    std::mt19937_64 rng(seed);
+    int step = 0;
+    for (int e = 0; e < epochs; ++e) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = n - 1; i > 0; --i) {
+            int j = (int)(rng() % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        HIPCK(hipMemcpyAsync(s + o_perm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+        for (int b = 0; b < nbatch; ++b) {
+            int nbt = std::min(batch, n - b * batch);
+            launch_mlp_gather(st, x, t, (int*)(s + o_perm) + (size_t)b * batch, nbt, (float*)(s + o_xb),
+                              (float*)(s + o_tb));
+            launch_mlp_grad(st, theta, nbt, (float*)(s + o_xb), (float*)(s + o_tb), (float*)(s + o_part),
+                            (float*)(s + o_lp), (float*)(s + o_grad), (float*)(s + o_loss) + b);
+            launch_mlp_adam(st, theta, (float*)(s + o_grad), m, v, ++step, lr, 0.9f, 0.999f, 1e-8f);
+        }
+        LAUNCHCK();
+        if (loss_curve) {
+            HIPCK(hipMemcpyAsync(losses.data(), s + o_loss, sizeof(float) * nbatch, hipMemcpyDeviceToHost, st));
+            HIPCK(hipStreamSynchronize(st));
+            double acc = 0.0;
+            for (int b = 0; b < nbatch; ++b) acc += (double)losses[b] * std::min(batch, n - b * batch);
+            loss_curve[e] = (float)(acc / n);
+        }
+    }
+    HIPCK(hipStreamSynchronize(st));
+    return CDWAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal helpers shared by the gfx950 kernels of the CD-WAC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdwac {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+// Lane layouts of the two matrix-core forms used here (gfx950, wave64):
+//  v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+//    D[i][j] in lane j + 16 (i % 4), element i / 4 (rows interleaved by 4).
+//  v_mfma_f32_32x32x16_bf16: A[i][k] in lane i + 32 (k / 8), element k % 8;
+//    B[k][j] in lane j + 32 (k / 8), element k % 8; D[i][j] in lane
+//    j + 32 ((i / 4) % 2), element 4 (i / 8) + i % 4.
+// Tile edge used for every padded dimension (auxiliary index, columns).
+constexpr int kPad = 128;
+// Block size of the blocked symmetric sweep (Gauss-Jordan) inversion.
+constexpr int kNb = 64;
+// Largest number of Pade reference points (one wave lane per point).
+constexpr int kMaxPade = 64;
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---- bf16 split: x ~= hi + lo with hi = rn(x), lo = rn(x - hi) ------------
+__device__ inline uint16_t bf16_bits(float x) {
+    __bf16 h = (__bf16)x;                 // round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Element types of the split operands: 0 = bf16 (8-bit significand),
+// 1 = fp16 (11-bit significand; callers scale the values into its range).
+template <int ET>
+struct Elem;
+template <>
+struct Elem<0> {
+    typedef v8bf vec;
+    __device__ static uint16_t bits(float x) { return bf16_bits(x); }
+    __device__ static float val(uint16_t b) { return bf16_float(b); }
+    __device__ static v16f mfma(vec a, vec b, v16f c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Elem<1> {
+    typedef v8h vec;
+    __device__ static uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+    __device__ static float val(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+    __device__ static v16f mfma(vec a, vec b, v16f c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// ---- complex double ---------------------------------------------------------
+struct cplx {
+    double re, im;
+};
+__host__ __device__ inline cplx cmk(double r, double i) { return cplx{r, i}; }
+__host__ __device__ inline cplx operator+(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplx operator-(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplx operator*(cplx a, cplx b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
+// Division with Smith's scaling (avoids overflow in |b|^2).
+__host__ __device__ inline cplx operator/(cplx a, cplx b) {
+    if (fabs(b.re) >= fabs(b.im)) {
+        double r = b.im / b.re, d = b.re + b.im * r;
+        return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+    } else {
+        double r = b.re / b.im, d = b.re * r + b.im;
+        return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+    }
+}
+__host__ __device__ inline bool cfinite(cplx a) { return isfinite(a.re) && isfinite(a.im); }
+
+// ---- XCD-aware tile order ---------------------------------------------------
+// Workgroups are handed to the 8 XCDs round robin.  Remapping the linear
+// block id so that XCD x receives a contiguous run of tiles keeps the tiles
+// that share operand panels on the same L2.
+__device__ inline int xcd_remap(int bid, int nblocks) {
+    constexpr int kXcd = 8;
+    int per = nblocks / kXcd;
+    int full = per * kXcd;
+    if (bid >= full) return bid;
+    return (bid % kXcd) * per + bid / kXcd;
+}
+
+}  // namespace cdwac

@@ -1,0 +1,289 @@
+// Self-energy and quasiparticle root on the GPU, FP64 (Sec. 2.3 Eqs.
+// In_term, Rn_term, ffact, cdselfe; Eq. qp_eq; Sec. 3.4).
+//
+//   I_n(w) = (1/pi) sum_m sum_k w_k W^c_nm(i w_k) a_m / (a_m^2 + w_k^2),  a_m = w - eps_m
+//            (the imaginary-axis integral folded over +-w', W^c even and real there)
+//   R_n(w) = sum_m f_m Re T_nm(|a_m| + i eta),  f_m of Eq. (ffact) with theta(0) = 1/2
+//   Sigma_n(w) = Sigma^x_n + R_n(w) - I_n(w)
+//
+// One workgroup per state; every thread runs the same root-search control
+// flow on block-reduced values.  Root search: secant from eps_n (or from the
+// learned seed) and one fixed-point step; fallback: scan the window at 0.01 Ha,
+// bisect every upward sign change with |f| < 0.1 Ha on both sides and keep the
+// root of largest Z (then the one nearest eps_n).
+#include "common.h"
+#include "kernels.h"
+
+namespace cdwac {
+
+constexpr double kScanStep = 0.01, kScanFmax = 0.1, kBisectTol = 1e-12, kZStep = 1e-4, kFTol = 1e-9;
+constexpr int kQpThreads = 256, kMaxFreq = 512;
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ inline double block_sum(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kQpThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double theta(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? 0.0 : 0.5); }
+
+struct Shared {
+    double red[kQpThreads];
+    double freq[kMaxFreq];
+    double weight[kMaxFreq];
+    float h1[64];
+    float h2[64];
+};
+
+// I_n(omega) and Re R_n(omega) for state s.
+__device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R) {
+    const int nf = A.n_freq;
+    const double* W = A.w_im + (int64_t)s * A.n_mo * nf;
+    double isum = 0.0;
+    for (int m = threadIdx.x; m < A.n_mo; m += kQpThreads) {
+        double am = omega - A.eps[m];
+        double am2 = am * am;
+        const double* wm = W + (int64_t)m * nf;
+        double acc = 0.0;
+        for (int k = 0; k < nf; ++k) acc += sh.weight[k] * wm[k] * (am / (am2 + sh.freq[k] * sh.freq[k]));
+        isum += acc;
+    }
+    double rsum = 0.0;
+    const int m0 = A.m0[s], m1 = A.m1[s], foff = A.fit_off[s];
+    for (int m = m0 + threadIdx.x; m < m1; m += kQpThreads) {
+        double em = A.eps[m];
+        double fm = -theta(A.eps_f - em) * theta(em - omega) + theta(em - A.eps_f) * theta(omega - em);
+        if (fm == 0.0) continue;
+        const int f = foff + (m - m0);
+        const double* a = A.coef + (int64_t)f * A.n_pts * 2;
+        const double* nd = A.node + (int64_t)f * A.n_pts * 2;
+        const int p = A.nterm[f];
+        cplx z = cmk(fabs(em - omega), A.eta);
+        cplx u = z * z;
+        cplx val = cmk(0.0, 0.0);
+        if (p > 0) {
+            cplx t = cmk(1.0, 0.0);
+            for (int q = p - 1; q >= 1; --q)
+                t = cmk(1.0, 0.0) + (cmk(a[2 * q], a[2 * q + 1]) * (u - cmk(nd[2 * q - 2], nd[2 * q - 1]))) / t;
+            val = cmk(a[0], a[1]) / t;
+        }
+        rsum += fm * val.re;
+    }
+    I = block_sum(isum, sh.red) / kPi;
+    R = block_sum(rsum, sh.red);
+}
+
+__device__ inline double sigma_total(const QpArgs& A, int s, double omega, Shared& sh) {
+    double I, R;
+    sigma_terms(A, s, omega, sh, I, R);
+    return A.sigx[s] + R - I;
+}
+
+// Single-sample MLP 8 -> 64 -> 64 -> 1 (tanh) on standardised features.
+__device__ float mlp_one(const float* __restrict__ th, const float* x, Shared& sh) {
+    const float* W1 = th;
+    const float* b1 = W1 + 64 * 8;
+    const float* W2 = b1 + 64;
+    const float* b2 = W2 + 64 * 64;
+    const float* W3 = b2 + 64;
+    const float* b3 = W3 + 64;
+    if (threadIdx.x < 64) {
+        float a = b1[threadIdx.x];
+        for (int i = 0; i < 8; ++i) a += W1[threadIdx.x * 8 + i] * x[i];
+        sh.h1[threadIdx.x] = tanhf(a);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        float a = b2[threadIdx.x];
+        for (int i = 0; i < 64; ++i) a += W2[threadIdx.x * 64 + i] * sh.h1[i];
+        sh.h2[threadIdx.x] = tanhf(a);
+    }
+    __syncthreads();
+    float y = b3[0];
+    for (int i = 0; i < 64; ++i) y += W3[i] * sh.h2[i];
+    __syncthreads();
+    return y;
+}
+
+__global__ __launch_bounds__(kQpThreads) void k_qp_solve(QpArgs A, QpOut* __restrict__ out) {
+    __shared__ Shared sh;
+    const int s = blockIdx.x;
+    for (int k = threadIdx.x; k < A.n_freq; k += kQpThreads) {
+        sh.freq[k] = A.freq[k];
+        sh.weight[k] = A.weight[k];
+    }
+    __syncthreads();
+    const double e_n = A.eps[A.state_idx[s]];
+    const double vxc = A.vxc[s];
+    const double lo = A.win_lo[s], hi = A.win_hi[s];
+    int n_eval = 0, flags = 0;
+    auto f = [&](double x) {
+        ++n_eval;
+        return x - e_n - sigma_total(A, s, x, sh) + vxc;
+    };
+    auto z_factor = [&](double x) {
+        double fp = f(x + kZStep);
+        double fm = f(x - kZStep);
+        return 2.0 * kZStep / (fp - fm);
+    };
+
+    double root = 0.0, zf = 0.0;
+    bool done = false;
+    double w0 = e_n, f0 = 0.0, w1 = 0.0;
+    bool seeded = false;
+    if (A.use_mlp) {
+        // features: eps_n, eps_F, Sigma^x - v^xc, Re Sigma^c at eps_n + {0, 1/8, 1/4, 3/8},
+        // fixed-point guess Sigma^x - v^xc + Re Sigma^c(eps_n)
+        float feat[8];
+        double sc[4];
+        for (int j = 0; j < 4; ++j) {
+            ++n_eval;
+            sc[j] = sigma_total(A, s, e_n + 0.125 * j, sh) - A.sigx[s];
+        }
+        double d0 = A.sigx[s] - vxc;
+        double raw[8] = {e_n, A.eps_f, d0, sc[0], sc[1], sc[2], sc[3], d0 + sc[0]};
+        for (int i = 0; i < 8; ++i) feat[i] = (float)((raw[i] - A.mlp_mu[i]) / A.mlp_sd[i]);
+        float y = mlp_one(A.mlp_theta, feat, sh);
+        double seed = e_n + (double)y * A.mlp_out_sd + A.mlp_out_mu;
+        if (seed >= lo && seed <= hi) {
+            double fs = f(seed);
+            if (fabs(fs) <= A.mlp_accept) {
+                root = seed;
+                zf = z_factor(seed);
+                flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
+                done = true;
+            } else {
+                w0 = seed;
+                f0 = fs;
+                w1 = w0 - f0;
+                seeded = true;
+            }
+        }
+    }
+    if (!done && !seeded) {
+        w0 = e_n;
+        f0 = f(w0);
+        w1 = w0 - f0;
+    }
+    if (!done) {
+        bool ok = false;
+        if (lo <= w1 && w1 <= hi) {
+            double f1 = f(w1);
+            for (int it = 0; it < A.qp_maxit; ++it) {
+                if (f1 == f0) break;
+                double w2 = w1 - f1 * (w1 - w0) / (f1 - f0);
+                if (!(lo <= w2 && w2 <= hi)) break;
+                w0 = w1;
+                f0 = f1;
+                w1 = w2;
+                f1 = f(w1);
+                if (fabs(w1 - w0) < A.qp_tol && fabs(f1) < kFTol) {
+                    ok = true;
+                    break;
+                }
+            }
+        }
+        if (ok) {
+            double z = z_factor(w1);
+            if (0.0 < z && z <= 1.0) {
+                root = w1;
+                zf = z;
+                done = true;
+            }
+        }
+    }
+    if (!done) {
+        flags |= CDWAC_FLAG_FALLBACK_DEV;
+        const int n = (int)ceil((hi - lo) / kScanStep);
+        bool have = false;
+        double best_z = 0.0, best_d = 0.0, best_r = 0.0;
+        double xa = lo, fa = f(xa);
+        for (int j = 0; j < n; ++j) {
+            double xb = lo + (hi - lo) * (j + 1) / n;
+            double fb = f(xb);
+            if (fa <= 0.0 && 0.0 < fb && fabs(fa) < kScanFmax && fabs(fb) < kScanFmax) {
+                double a = xa, b = xb;
+                while (b - a > kBisectTol) {
+                    double c = 0.5 * (a + b);
+                    if (f(c) <= 0.0) a = c;
+                    else b = c;
+                }
+                double r = 0.5 * (a + b);
+                double z = z_factor(r);
+                double d = -fabs(r - e_n);
+                if (!have || z > best_z || (z == best_z && d > best_d)) {
+                    have = true;
+                    best_z = z;
+                    best_d = d;
+                    best_r = r;
+                }
+            }
+            xa = xb;
+            fa = fb;
+        }
+        if (have) {
+            root = best_r;
+            zf = best_z;
+        } else {
+            root = nan("");
+            zf = nan("");
+            flags |= CDWAC_FLAG_NOROOT_DEV;
+        }
+    }
+    double I = 0.0, R = 0.0;
+    if (!(flags & CDWAC_FLAG_NOROOT_DEV)) sigma_terms(A, s, root, sh, I, R);
+    if (threadIdx.x == 0) {
+        QpOut o;
+        o.qp = root;
+        o.z = zf;
+        o.sigma_x = A.sigx[s];
+        o.sigma_c = (flags & CDWAC_FLAG_NOROOT_DEV) ? nan("") : R - I;
+        o.residual = (flags & CDWAC_FLAG_NOROOT_DEV) ? nan("") : root - e_n - (A.sigx[s] + R - I) + vxc;
+        o.n_evals = n_eval;
+        o.flags = flags;
+        out[s] = o;
+    }
+}
+
+// sigma[s][k] = Re Sigma_n(omega[s][k]) (+ I and R terms).
+__global__ __launch_bounds__(kQpThreads) void k_sigma_eval(QpArgs A, int n_omega, const double* __restrict__ omega,
+                                                           double* __restrict__ sigma, double* __restrict__ iterm,
+                                                           double* __restrict__ rterm) {
+    __shared__ Shared sh;
+    const int k = blockIdx.x, s = blockIdx.y;
+    for (int q = threadIdx.x; q < A.n_freq; q += kQpThreads) {
+        sh.freq[q] = A.freq[q];
+        sh.weight[q] = A.weight[q];
+    }
+    __syncthreads();
+    const int64_t o = (int64_t)s * n_omega + k;
+    double I, R;
+    sigma_terms(A, s, omega[o], sh, I, R);
+    if (threadIdx.x == 0) {
+        sigma[o] = A.sigx[s] + R - I;
+        if (iterm) iterm[o] = I;
+        if (rterm) rterm[o] = R;
+    }
+}
+
+int qp_max_freq() { return kMaxFreq; }
+
+void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out) {
+    hipLaunchKernelGGL(k_qp_solve, dim3(a.n_states), dim3(kQpThreads), 0, s, a, out);
+}
+
+void launch_sigma(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* sigma,
+                  double* iterm, double* rterm) {
+    if (n_omega <= 0) return;
+    hipLaunchKernelGGL(k_sigma_eval, dim3(n_omega, a.n_states), dim3(kQpThreads), 0, s, a, n_omega, omega,
+                       sigma, iterm, rterm);
+}
+
+}  // namespace cdwac

@@ -1,0 +1,109 @@
+// Launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdwac {
+
+constexpr int CDWAC_FLAG_NOROOT_DEV = 1;
+constexpr int CDWAC_FLAG_FALLBACK_DEV = 2;
+constexpr int CDWAC_FLAG_MLP_ACCEPTED_DEV = 4;
+
+// Everything the self-energy / root kernels read (device pointers unless noted).
+struct QpArgs {
+    int n_mo, n_states, n_freq, n_pts;
+    const double* eps;
+    const double* freq;
+    const double* weight;
+    const double* w_im;      // [S][n_mo][n_freq]
+    const double* coef;      // [n_fit][n_pts][2]
+    const double* node;      // [n_fit][n_pts][2]
+    const int* nterm;        // [n_fit]
+    const int* fit_off;      // [S]
+    const int* m0;           // [S]
+    const int* m1;           // [S]
+    const int* state_idx;    // [S]
+    const double* sigx;      // [S]
+    const double* vxc;       // [S]
+    const double* win_lo;    // [S]
+    const double* win_hi;    // [S]
+    double eta, eps_f, qp_tol;
+    int qp_maxit;
+    int use_mlp;
+    double mlp_accept;
+    const float* mlp_theta;  // [4801]
+    float mlp_mu[8], mlp_sd[8];
+    float mlp_out_mu, mlp_out_sd;
+};
+
+struct QpOut {
+    double qp, z, sigma_x, sigma_c, residual;
+    int32_t n_evals, flags;
+};
+
+// precision codes (same values as cdwac_prec)
+constexpr int PREC_P64 = 0, PREC_B16X3 = 1, PREC_B16 = 2, PREC_F16X3 = 3;
+inline int prec_elem(int prec) { return prec == PREC_F16X3 ? 1 : 0; }
+
+// k_stage.hip
+void launch_absmax(hipStream_t s, const double* src, int64_t lds, int rows, int64_t cols, uint32_t* amax, int* err);
+void launch_weights(hipStream_t s, const double* eps, int n_occ, int n_virt, double spin, const double* zr,
+                    const double* zi, const int* part, int n_f, int64_t kpad, double* cw64, float* cw32,
+                    uint32_t* cmax);
+void launch_scales_pi(hipStream_t s, const uint32_t* amax, int n_f, double* sf);
+void launch_scale_weights(hipStream_t s, float* cw32, int64_t kpad, int n_f, const double* cfac);
+void launch_scales_w(hipStream_t s, const uint32_t* lmax, int n_f, double* sf, double* lam_scale, double* w_unscale);
+void launch_split_pad(hipStream_t s, int et, const double* src, int64_t lds, int rows, int64_t cols,
+                      const double* scale, uint16_t* hi, uint16_t* lo, double* f64, int rpad, int64_t cpad);
+void launch_transpose_b(hipStream_t s, int et, const double* onm, int S, int N, int n_mo, const int* rowsel,
+                        int nrows, const double* scale, double* bt64, uint16_t* bh, uint16_t* bl, int cpad,
+                        int npad, uint32_t* bmax, int* err);
+void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, int n_occ, double* sx);
+void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax);
+void launch_split_lambda(hipStream_t s, int et, const double* lam, int npad, int n_f, const double* lam_scale,
+                         uint16_t* lh, uint16_t* ll);
+void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out);
+void launch_reduce_w(hipStream_t s, const double* partial_im, const double* partial_re, int ni, int cpad,
+                     int cfpad, int n_im, int n_re, int ncols, int nfit, double* w_im, double* w_re);
+
+// k_dense.hip
+void launch_pi(hipStream_t s, int prec, int npad, int64_t kpad, int n_f, const double* x64, const uint16_t* xh,
+               const uint16_t* xl, const double* cw64, const float* cw32, const double* pi_unscale,
+               const int* idflag, double* E);
+int w_partial_blocks(int prec, int npad);
+void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* lam64, const uint16_t* lh,
+              const uint16_t* ll, const double* bt64, const uint16_t* bh, const uint16_t* bl, int cpad,
+              const double* w_unscale, double* partial);
+
+// k_sweep.hip
+void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dinv_r,
+                  double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c, double* qbuf_c, int* err);
+
+// k_thiele.hip
+void launch_thiele_fit(hipStream_t s, int n_fit, int n_pts, const double* u, const double* w, double tol,
+                       double* coef, double* node, int* nterm);
+void launch_thiele_eval(hipStream_t s, int n_fit, int n_pts, const double* coef, const double* node,
+                        const int* nterm, int n_x, const double* x, double* out);
+void launch_gather_refs(hipStream_t s, int n_fit, const int* fit_s, const int* fit_m, int n_mo, int n_freq,
+                        const double* w_im, const double* w_re, const double* freq, const int* ref_im_idx,
+                        int n_im, const double* ref_re, int n_re, double eta_ref, double* u, double* w);
+
+// k_qp.hip
+int qp_max_freq();
+void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out);
+void launch_sigma(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* sigma,
+                  double* iterm, double* rterm);
+
+// k_mlp.hip
+constexpr int kMlpParams = 4801;
+int mlp_grad_blocks(int n);
+void launch_mlp_forward(hipStream_t s, const float* theta, int n, const float* x, float* y);
+void launch_mlp_grad(hipStream_t s, const float* theta, int n, const float* x, const float* t, float* partial,
+                     float* loss_partial, float* grad, float* loss);
+void launch_mlp_adam(hipStream_t s, float* theta, const float* grad, float* m, float* v, int step, float lr,
+                     float b1, float b2, float eps);
+void launch_mlp_gather(hipStream_t s, const float* x, const float* t, const int* idx, int n, float* xb,
+                       float* tb);
+
+}  // namespace cdwac

@@ -118,12 +118,17 @@ def make_system(n_mo: int, n_occ: int, n_aux: int, n_core: int, sigma: float,
 
 
 #: Workload shapes (energies in the recipe above).  ``sigma=None`` means
-#: sigma = sqrt(20 / K) with K = n_occ * n_virt, i.e. the same screening
-#: strength K sigma^2 as the 600-orbital case.
+#: sigma = sqrt(1.25 / K) with K = n_occ * n_virt: the screening strength
+#: K sigma^2 of the 60-orbital case is kept at every size.  With it the
+#: largest RPA excitation stays near 70 eV; at K sigma^2 = 20 it rises to
+#: ~250 eV and valence-hole + plasmon satellites fall inside the core window,
+#: leaving several core states without a distinct quasiparticle root.  The
+#: same rule keeps the core coupling n_mo * n_aux * sigma^2 * kappa^2 fixed,
+#: since n_mo * n_aux / K is 24 for every workload below.
 WORKLOADS = {
     "fp64_1core_nmo60": dict(n_mo=60, n_occ=10, n_aux=200, n_core=1, sigma=0.05,
                              n_freq=32, n_pade=16, window_ev=(-320.0, -260.0), seed=1),
-    "acene_nmo600": dict(n_mo=600, n_occ=100, n_aux=2000, n_core=6, sigma=0.02,
+    "acene_nmo600": dict(n_mo=600, n_occ=100, n_aux=2000, n_core=6, sigma=None,
                          n_freq=64, n_pade=24, window_ev=30.0, seed=2),
     "precision_naux5000": dict(n_mo=1500, n_occ=250, n_aux=5000, n_core=16, sigma=None,
                                n_freq=64, n_pade=24, window_ev=30.0, seed=3),
@@ -132,11 +137,14 @@ WORKLOADS = {
 }
 
 
+SCREENING = 1.25   # K sigma^2 of the 60-orbital workload
+
+
 def workload_sigma(spec: dict) -> float:
     if spec.get("sigma") is not None:
         return float(spec["sigma"])
     k = spec["n_occ"] * (spec["n_mo"] - spec["n_occ"])
-    return math.sqrt(20.0 / k)
+    return math.sqrt(SCREENING / k)
 
 
 def make_workload(name: str, seed: Optional[int] = None, kappa: float = 0.2) -> System:
@@ -159,5 +167,5 @@ def batch_specs(n_sys: int = 48, seed: int = 400):
         n_aux = int(round(3.3 * n_mo))
         k = n_occ * (n_mo - n_occ)
         out.append(dict(n_mo=n_mo, n_occ=n_occ, n_aux=n_aux, n_core=n_core,
-                        sigma=math.sqrt(20.0 / k), seed=seed + j))
+                        sigma=math.sqrt(SCREENING / k), seed=seed + j))
     return out

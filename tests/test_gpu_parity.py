@@ -1,0 +1,218 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances:
+* FP64 path: Pi to 1e-12 of max|Pi|; W^c to 1e-10 of max|W| per (n, m)
+  (Lambda = eps^-1 - I loses ~5 digits where |Lambda| ~ 1e-5, at the top
+  imaginary nodes); Sigma and the QP energies to 1e-9 relative.
+* bf16 hi/lo path: QP energies within 1 meV (3.675e-5 Ha) of the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import cases
+from oracle import cdwac_ref as R
+
+pytestmark = pytest.mark.gpu
+
+MEV = 1e-3 / 27.211386245988
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    from paper_2305_15955_amd import cdwac
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = cdwac.Cdwac(0)
+    yield c
+    c.close()
+
+
+def run(lib, case, prec="p64", pade_tol=None, vxc=None, **kw):
+    sysc, keep = lib.make_system(case.system, vxc=vxc)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, eta_ref=case.eta_ref,
+                                pade_tol=case.pade_tol if pade_tol is None else pade_tol, prec=prec, **kw)
+    lib.cdwac_prepare(sysc, prm)
+    return sysc, prm, (keep, arrs)
+
+
+# --------------------------------------------------------------------- Pi
+
+@pytest.mark.parametrize("prec,tol", [("p64", 1e-12), ("b16x3", 3e-5), ("f16x3", 1e-6)])
+def test_polarizability_ragged(lib, prec, tol):
+    case = cases.ragged()
+    s = case.system
+    sysc, keep = lib.make_system(s)
+    zs = [0.05j, 1.3j, 40.0j, 0.7 + 1e-3j, 3.1 + 0.2j]
+    got = lib.cdwac_polarizability(sysc, zs, prec=prec)
+    for j, z in enumerate(zs):
+        ref = R.polarizability(s.o_ia, s.eps, s.n_occ, z, s.spin)
+        err = np.max(np.abs(got[j] - ref)) / np.max(np.abs(ref))
+        assert err < tol, (z, err)
+
+
+def test_polarizability_single_element():
+    """n_aux = 1 and K = 1: one padded tile, everything else zero."""
+    import torch
+    from paper_2305_15955_amd import cdwac
+    case = cases.one_transition()
+    c = cdwac.Cdwac(0)
+    sysc, keep = c.make_system(case.system)
+    got = c.cdwac_polarizability(sysc, [0.3j, 0.5 + 0.01j])
+    s = case.system
+    for j, z in enumerate([0.3j, 0.5 + 0.01j]):
+        ref = R.polarizability(s.o_ia, s.eps, s.n_occ, z, s.spin)
+        np.testing.assert_allclose(got[j], ref, rtol=1e-13)
+    c.close()
+
+
+# ----------------------------------------------------------- W, Sigma, QP
+
+def test_w_table_fp64_ragged(lib):
+    case = cases.ragged()
+    o = cases.oracle(case)
+    run(lib, case, "p64")
+    s = case.system
+    w_im, w_re, sx, (m0, m1) = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+    scale = np.max(np.abs(o.w_im), axis=2, keepdims=True)
+    assert np.max(np.abs(w_im - o.w_im) / scale) < 1e-10
+    np.testing.assert_allclose(sx, o.sigma_x, rtol=1e-13)
+    f = 0
+    for n in range(s.n_states):
+        for m in range(m0[n], m1[n]):
+            ref = o.w_re[n, m, :]
+            err = np.max(np.abs(w_re[f] - ref)) / np.max(np.abs(ref))
+            assert err < 1e-10, (n, m, err)
+            f += 1
+    assert f == w_re.shape[0]
+
+
+@pytest.mark.parametrize("which", ["ragged", "fp64_1core_nmo60", "one_transition"])
+def test_sigma_and_qp_fp64(lib, which):
+    case = {"ragged": cases.ragged, "one_transition": cases.one_transition}.get(
+        which, lambda: cases.workload(which))()
+    o = cases.oracle(case)
+    run(lib, case, "p64")
+    s = case.system
+    oms = np.array([[s.eps[s.state_idx[n]] + d for d in (-0.3, -0.05, 0.0, 0.2, 0.45)]
+                    for n in range(s.n_states)])
+    sig = lib.cdwac_sigma(oms)
+    for n in range(s.n_states):
+        for k in range(oms.shape[1]):
+            ref = o.sigma(n, oms[n, k])
+            assert abs(sig[n, k] - ref) <= 1e-9 * abs(ref) + 1e-12, (n, k, sig[n, k], ref)
+    out = lib.cdwac_qp(s.n_states)
+    for n, r in enumerate(o.solve_all()):
+        g = out[n]
+        assert g["flags"] == r[3]
+        assert abs(g["qp"] - r[0]) <= 1e-9 * abs(r[0]), (n, g["qp"], r[0])
+        assert abs(g["z"] - r[1]) < 1e-6
+        assert abs(g["residual"]) < 1e-8
+        assert g["sigma_x"] == pytest.approx(o.sigma_x[n], rel=1e-13)
+
+
+@pytest.mark.parametrize("prec,tol_mev", [("f16x3", 1.0)])
+def test_qp_reduced_precision_within_1mev(lib, prec, tol_mev):
+    for case in (cases.ragged(), cases.workload("fp64_1core_nmo60")):
+        o = cases.oracle(case)
+        run(lib, case, prec)
+        out = lib.cdwac_qp(case.system.n_states)
+        for n, r in enumerate(o.solve_all()):
+            assert abs(out[n]["qp"] - r[0]) <= tol_mev * MEV, (case.name, n, out[n]["qp"], r[0])
+
+
+def test_imaginary_only_reference_set(lib):
+    """Valence setting F_wac = F_Im: no near-real points."""
+    case = cases.ragged()
+    case.ref_re = np.zeros(0)
+    case.ref_im = np.arange(0, 24, 2, dtype=np.int32)
+    o = cases.oracle(case)
+    run(lib, case, "p64")
+    out = lib.cdwac_qp(case.system.n_states)
+    for n, r in enumerate(o.solve_all()):
+        if r[3] & R.FLAG_NOROOT:
+            assert out[n]["flags"] & R.FLAG_NOROOT
+        else:
+            assert abs(out[n]["qp"] - r[0]) <= 1e-9 * abs(r[0])
+
+
+def test_vxc_override_and_fallback(lib):
+    case = cases.workload("fp64_1core_nmo60")
+    o = cases.oracle(case)
+    run(lib, case, "p64")
+    # shifted v^xc moves the root; same solver path on both sides
+    vx = o.vxc + 0.05
+    out = lib.cdwac_qp(1, vxc=vx)
+    e_n = case.system.eps[0]
+    ref = R.qp_solve(lambda x: x - e_n - o.sigma(0, x) + vx[0], e_n, case.lo[0], case.hi[0])
+    assert abs(out[0]["qp"] - ref[0]) <= 1e-9 * abs(ref[0]) and out[0]["flags"] == ref[3]
+    # no root in the window: v^xc far off
+    vx = o.vxc + 5.0
+    out = lib.cdwac_qp(1, vxc=vx)
+    assert math.isnan(out[0]["qp"]) and out[0]["flags"] & R.FLAG_NOROOT
+
+
+# ------------------------------------------------------------------ Pade
+
+def test_pade_fit_eval_matches_oracle(lib):
+    """Greedy fits of few-pole data with the stop rule (the sequence of
+    chosen points, the term count and the model values agree), and of
+    many-pole data that needs every point (tol = 0)."""
+    rng = np.random.default_rng(5)
+    nf = 37
+    x = (np.linspace(0.0, 11.0, 9) + 1e-3j) ** 2
+    xx = np.tile(x, (nf, 1))
+    # the second set interpolates 5 poles with exactly 10 points, where the
+    # FP64 interpolant is still well conditioned
+    for tol, poles, n_half in ((1e-9, (1, 6), 12), (0.0, (5, 6), 5)):
+        z = np.concatenate([1j * np.geomspace(0.05, 40, n_half), np.linspace(0, 12, n_half) + 1e-3j])
+        u = np.tile(z * z, (nf, 1))
+        npts = 2 * n_half
+        w = np.zeros((nf, npts), complex)
+        for f in range(nf):
+            for _ in range(rng.integers(*poles)):
+                om, c = rng.uniform(0.3, 15.0), rng.uniform(0.01, 0.5)
+                w[f] += -c * om / (om * om - u[f])
+        got, nt = lib.cdwac_pade_fit_eval(u, w, tol, xx)
+        for f in range(nf):
+            coef, nodes = R.thiele_greedy(u[f], w[f], tol)
+            ref = R.thiele_eval(coef, nodes, x)
+            assert nt[f] == len(coef), (tol, f)
+            assert np.max(np.abs(got[f] - ref)) <= 1e-8 * np.max(np.abs(ref)), (tol, f)
+
+
+def test_pade_single_pole_stops_after_two_terms(lib):
+    z = np.concatenate([1j * np.geomspace(0.1, 20, 6), np.linspace(0.0, 5.0, 6) + 1e-3j])
+    u = (z * z)[None, :]
+    w = -0.7 * 2.3 / (2.3 ** 2 - u)
+    got, nt = lib.cdwac_pade_fit_eval(u, w, 1e-12, u)
+    assert nt[0] == 2
+    np.testing.assert_allclose(got, w, rtol=1e-12)
+
+
+# ------------------------------------------------------------ error paths
+
+def test_error_paths(lib):
+    import torch
+    from paper_2305_15955_amd import cdwac
+    case = cases.ragged()
+    s = case.system
+    fresh = cdwac.Cdwac(0)
+    with pytest.raises(cdwac.CdwacError) as e:
+        fresh.cdwac_qp(s.n_states)
+    assert e.value.code == cdwac.CDWAC_ESTATE
+    bad = cases.ragged()
+    bad.system.eps = bad.system.eps.copy()
+    bad.system.eps[3] = bad.system.eps[2]
+    with pytest.raises(cdwac.CdwacError) as e:
+        run(fresh, bad, "p64")
+    assert e.value.code == cdwac.CDWAC_EINVAL
+    nan = cases.ragged()
+    nan.system.o_ia = nan.system.o_ia.copy()
+    nan.system.o_ia[5, 7] = np.nan
+    with pytest.raises(cdwac.CdwacError) as e:
+        run(fresh, nan, "b16x3")
+    assert e.value.code == cdwac.CDWAC_EINVAL
+    fresh.close()
