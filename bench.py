@@ -1,0 +1,196 @@
+#!/usr/bin/env python
+"""Throughput of the CD-WAC core-level G0W0 path on one MI355X.
+
+One step = one full solve through the C ABI (cdwac_solve): polarizability on
+the imaginary grid and at the near-real Pade references, dielectric
+inversion, W contraction, exchange, greedy Thiele fits and the QP root of
+every core state.  Inputs (KS energies, RI coefficients) are seeded synthetic
+arrays already resident in HBM when the timed region starts.
+
+Prints one JSON line.  value = core QP energies per second of the whole job
+(reduced-precision contractions, learned seed if a model is installed);
+also reported: the plain FP64 GPU path, the per-state error of the reduced
+path against it in meV, per-stage times from HIP events on the library's
+stream, the roofline of the polarizability kernel, and the FP64 oracle timed
+on a bounded sample of the same workload on the host CPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f16x3": 2.5e15, "b16x3": 2.5e15, "b16": 2.5e15, "p64": 78.6e12}   # dense MFMA, FLOP/s
+PRODUCTS = {"f16x3": 3, "b16x3": 3, "b16": 1, "p64": 1}
+MODEL_PATH = os.path.join(ROOT, "paper_2305_15955_amd", "seed_model.npz")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_inputs(name):
+    from paper_2305_15955_amd import grids, synth
+    spec = synth.WORKLOADS[name]
+    s = synth.make_workload(name)
+    freq, wts = grids.gauss_legendre_imag(spec["n_freq"])
+    lo, hi = grids.windows(s.eps, s.state_idx, spec["window_ev"])
+    nim = spec["n_pade"] // 2
+    ref_im = grids.imag_ref_indices(len(freq), nim)
+    ref_re = grids.generic_refs(s.eps, s.n_occ, lo, spec["n_pade"] - nim)
+    return spec, s, freq, wts, ref_im, ref_re, lo, hi
+
+
+def cpu_baseline(s, freq, n_re, n_states):
+    """The oracle's wmatrix at one imaginary node, full size, timed; scaled to
+    QP energies per second: the oracle's prepare runs n_freq such real
+    evaluations and n_re complex ones (4x the real flops), its QP loop is
+    negligible next to them."""
+    from oracle import cdwac_ref as R
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    w = float(freq[len(freq) // 2])
+    t0 = time.perf_counter()
+    pi = R.polarizability(s.o_ia, s.eps, s.n_occ, 1j * w, s.spin)
+    lam = R.lambda_matrix(pi)
+    del pi
+    for st in range(n_states):
+        R.w_elements(s.o_nm[st], lam)
+    dt = time.perf_counter() - t0
+    t_job = dt * (len(freq) + 4 * n_re)
+    return {"value": n_states / t_job, "unit": "core QP energies/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"oracle wmatrix (Pi, Lambda, W for {n_states} states) at 1 of {len(freq)} "
+                       f"imaginary nodes, full size, {dt:.1f} s; job time scaled as "
+                       f"{len(freq)} real + {n_re} complex (4x) nodes = {t_job:.0f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="precision_naux5000")
+    ap.add_argument("--prec", default="f16x3", choices=["f16x3", "b16x3", "b16", "p64"])
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 GPU path")
+    ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
+              "multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_15955_amd import cdwac, synth
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    spec, s, freq, wts, ref_im, ref_re, lo, hi = build_inputs(args.workload)
+    log(f"inputs {args.workload}: n_aux={s.n_aux} n_mo={s.n_mo} K={s.o_ia.shape[1]} "
+        f"states={s.n_states} ({time.perf_counter() - t0:.1f} s)")
+    lib = cdwac.Cdwac(0)
+    o_ia = torch.from_numpy(s.o_ia).to(dev)
+    o_nm = torch.from_numpy(s.o_nm).to(dev)
+    torch.cuda.synchronize()
+
+    use_mlp = (not args.no_mlp) and os.path.exists(MODEL_PATH)
+    if use_mlp:
+        m = np.load(MODEL_PATH)
+        lib.cdwac_mlp_set_model(m["theta"], m["mu"], m["sd"], float(m["out_mu"]), float(m["out_sd"]))
+
+    def params(prec, mlp):
+        return lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec=prec,
+                               pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4)
+
+    sysc, keep = lib.make_system(s, o_ia_dev=o_ia, o_nm_dev=o_nm)
+    lib.cdwac_set_timing(True)
+
+    def run_steps(prec, mlp, warmup, steps):
+        prm, arrs = params(prec, mlp)
+        for i in range(warmup):
+            lib.cdwac_solve(sysc, prm)
+            log(f"warmup {prec} {i + 1}/{warmup} done")
+        stage_sum = {k: 0.0 for k in lib.STAGES}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = None
+        for i in range(steps):
+            out = lib.cdwac_solve(sysc, prm)
+            for k, v in lib.cdwac_get_timing().items():
+                stage_sum[k] += v
+            log(f"step {prec} {i + 1}/{steps} done")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / max(steps, 1)
+        return out, dt, {k: v / max(steps, 1) for k, v in stage_sum.items()}
+
+    out, dt, stages = run_steps(args.prec, use_mlp, args.warmup, args.steps)
+    qps = s.n_states / dt
+    res = {"metric": "core QP energies/sec at N_aux=5000 (mixed+MLP vs FP64), meV err, MFMA util",
+           "value": qps, "unit": "core QP energies/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": f"{args.prec}+fp64",
+           "data": "synthetic (seeded Gaussian RI coefficients, no molecule)",
+           "config": {"workload": args.workload, "n_aux": s.n_aux, "n_mo": s.n_mo, "n_occ": s.n_occ,
+                      "n_states": s.n_states, "n_freq": len(freq), "n_pade": len(ref_im) + len(ref_re),
+                      "contraction_precision": args.prec, "mlp_seed": use_mlp}}
+
+    # roofline of the dominant kernel (polarizability, one launch per step)
+    n_f = len(freq) + 2 * len(ref_re)
+    k_dim = s.o_ia.shape[1]
+    flops = float(n_f) * s.n_aux * (s.n_aux + 1) * k_dim        # lower-triangle SYRK, 2 flop/MAC
+    pi_s = stages["polarizability"] * 1e-3
+    achieved = flops / pi_s / 1e12
+    peak = PEAK[args.prec] / 1e12
+    npad = int(math.ceil(s.n_aux / 128.0) * 128)
+    issued = flops * PRODUCTS[args.prec] * (npad * (npad + 128) / 2) / (s.n_aux * (s.n_aux + 1) / 2)
+    res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                       "frac": achieved / peak, "traffic": None,
+                       "kernel": "k_pi_split" if args.prec != "p64" else "k_pi_f64",
+                       "algorithmic_flop_per_launch": flops, "launch_ms": pi_s * 1e3,
+                       "mfma_issued_frac": issued / pi_s / PEAK[args.prec]}
+    res["stages_ms"] = stages
+    res["qp_ev"] = [o["qp"] * synth.HARTREE_EV for o in out]
+    res["n_evals_mean"] = float(np.mean([o["n_evals"] for o in out]))
+
+    if args.fp64_steps > 0 and args.prec != "p64":
+        out64, dt64, st64 = run_steps("p64", False, 0, args.fp64_steps)
+        err = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(out, out64)]
+        res["fp64_path"] = {"value": s.n_states / dt64, "ms_per_step": dt64 * 1e3, "stages_ms": st64,
+                            "n_evals_mean": float(np.mean([o["n_evals"] for o in out64]))}
+        res["mev_err_vs_fp64"] = {"max": max(err), "mean": float(np.mean(err)), "per_state": err}
+        res["speedup_vs_fp64_path"] = dt64 / dt
+
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = 2 * a.numel() * 8
+
+    del o_ia, o_nm
+    lib.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample) ...")
+        res["cpu_baseline"] = cpu_baseline(s, freq, len(ref_re), s.n_states)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

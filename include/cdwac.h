@@ -190,8 +190,8 @@ int cdwac_get_timing(const cdwac_ctx *ctx, double *ms, int32_t n);
 /* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------
  * Parameter vector (CDWAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64],
  * b2[64], W3[1][64], b3[1].  Features of a state (Ha): eps_n, eps_F,
- * Sigma^x - v^xc, Re Sigma^c at eps_n + {0, 1/8, 1/4, 3/8}, and the
- * fixed-point guess Sigma^x - v^xc + Re Sigma^c(eps_n); the network predicts
+ * Sigma^x - v^xc, Re Sigma^c at eps_n + {-3, -1, 1, 3}/16, and the
+ * fixed-point guess Sigma^x - v^xc + (two central samples)/2; the network predicts
  * eps^QP - eps_n.  Inputs are standardised with (mu, sd) and the output is
  * y * out_sd + out_mu. */
 #define CDWAC_MLP_NIN 8

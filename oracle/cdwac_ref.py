@@ -96,6 +96,19 @@ def polarizability(o_ia: np.ndarray, eps: np.ndarray, n_occ: int, z: complex,
     return (o_ia * d[None, :]) @ o_ia.T
 
 
+def polarizability_entries(o_ia: np.ndarray, eps: np.ndarray, n_occ: int, z: complex,
+                           spin: float, pairs) -> np.ndarray:
+    """Selected elements Pi_PQ(z) of Eq. (piriv), one dot product each.
+
+    For sampled checks at sizes where the full matrix is out of reach.  Pin:
+    equals ``polarizability`` element by element on small inputs.
+    """
+    delta = transition_energies(eps, n_occ)
+    z = complex(z)
+    d = spin * (1.0 / (z - delta) - 1.0 / (z + delta))
+    return np.array([np.dot(o_ia[p] * d, o_ia[q]) for p, q in pairs])
+
+
 def lambda_matrix(pi: np.ndarray) -> np.ndarray:
     """Lambda = [I - Pi]^{-1} - I of Eq. (bigLambda), as (I - Pi)^{-1} Pi."""
     n = pi.shape[0]

@@ -139,16 +139,16 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_solve(QpArgs A, QpOut* __rest
     double w0 = e_n, f0 = 0.0, w1 = 0.0;
     bool seeded = false;
     if (A.use_mlp) {
-        // features: eps_n, eps_F, Sigma^x - v^xc, Re Sigma^c at eps_n + {0, 1/8, 1/4, 3/8},
-        // fixed-point guess Sigma^x - v^xc + Re Sigma^c(eps_n)
+        // features: eps_n, eps_F, Sigma^x - v^xc, Re Sigma^c at eps_n + {-3, -1, 1, 3}/16 Ha,
+        // fixed-point guess Sigma^x - v^xc + mean of the two central samples
         float feat[8];
         double sc[4];
         for (int j = 0; j < 4; ++j) {
             ++n_eval;
-            sc[j] = sigma_total(A, s, e_n + 0.125 * j, sh) - A.sigx[s];
+            sc[j] = sigma_total(A, s, e_n + (2 * j - 3) / 16.0, sh) - A.sigx[s];
         }
         double d0 = A.sigx[s] - vxc;
-        double raw[8] = {e_n, A.eps_f, d0, sc[0], sc[1], sc[2], sc[3], d0 + sc[0]};
+        double raw[8] = {e_n, A.eps_f, d0, sc[0], sc[1], sc[2], sc[3], d0 + 0.5 * (sc[1] + sc[2])};
         for (int i = 0; i < 8; ++i) feat[i] = (float)((raw[i] - A.mlp_mu[i]) / A.mlp_sd[i]);
         float y = mlp_one(A.mlp_theta, feat, sh);
         double seed = e_n + (double)y * A.mlp_out_sd + A.mlp_out_mu;

@@ -30,9 +30,14 @@ def build(system, n_freq, n_im, n_re, window_ev, name="case", pade_tol=1e-9):
 
 
 def ragged(seed=21):
-    """Several bf16 tiles and a ragged tail in every padded dimension."""
+    """Several matrix-core tiles and a ragged tail in every padded dimension.
+
+    32 Pade points (16 imaginary of 48 nodes, 16 near-real): with 12 points
+    this system's CD-WAC result is ~60 meV from full CD, with 32 it is within
+    0.14 meV, so the continuation is converged and not hypersensitive.
+    """
     s = synth.make_system(90, 15, 300, 3, 0.04, kappa=0.2, seed=seed)
-    return build(s, 24, 6, 6, 30.0, name="ragged_naux300")
+    return build(s, 48, 16, 16, 30.0, name="ragged_naux300")
 
 
 def workload(name):

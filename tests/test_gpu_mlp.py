@@ -1,0 +1,101 @@
+"""The learned QP seed: hand-written FP32 kernels against the FP64 reference,
+and what the trained network changes in the root search."""
+import os
+
+import numpy as np
+import pytest
+
+import cases
+from oracle import mlp_ref as M
+from paper_2305_15955_amd import synth
+
+pytestmark = pytest.mark.gpu
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2305_15955_amd",
+                     "seed_model.npz")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    from paper_2305_15955_amd import cdwac
+    assert torch.cuda.is_available()
+    c = cdwac.Cdwac(0)
+    yield c
+    c.close()
+
+
+def data(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 8))
+    t = np.sin(x[:, 0]) + 0.3 * x[:, 1] * x[:, 2] - 0.2 * x[:, 5]
+    return x, t
+
+
+def test_forward_matches_reference(lib):
+    x, _ = data(1000, 1)
+    theta = M.init_params(3)
+    theta[-1] = 0.2
+    y32 = lib.cdwac_mlp_forward(theta, x)
+    y64, _ = M.forward(theta.astype(np.float64), x.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(y32, y64, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 1000, 5003])
+def test_gradient_matches_reference(lib, n):
+    x, t = data(n, 2)
+    theta = M.init_params(4).astype(np.float32).astype(np.float64)
+    xf = x.astype(np.float32).astype(np.float64)
+    tf = t.astype(np.float32).astype(np.float64)
+    loss, g = lib.cdwac_mlp_grad(theta, xf, tf)
+    loss_ref, g_ref = M.loss_and_grad(theta, xf, tf)
+    assert loss == pytest.approx(loss_ref, rel=1e-5)
+    assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+
+
+def test_adam_step_matches_reference(lib):
+    import torch
+    rng = np.random.default_rng(5)
+    theta = rng.standard_normal(4801)
+    grad = rng.standard_normal(4801)
+    m = rng.standard_normal(4801) * 0.1
+    v = np.abs(rng.standard_normal(4801)) * 0.1
+    dev = torch.device("cuda", 0)
+    td, gd, md, vd = (torch.tensor(a, dtype=torch.float32, device=dev) for a in (theta, grad, m, v))
+    lib.cdwac_mlp_adam(td, gd, md, vd, 7, 1e-3)
+    th, mm, vv = theta.copy(), m.copy(), v.copy()
+    M.adam_step(th, grad, mm, vv, 7, 1e-3)
+    np.testing.assert_allclose(td.cpu().numpy(), th, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(md.cpu().numpy(), mm, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(vd.cpu().numpy(), vv, rtol=1e-5, atol=1e-7)
+
+
+def test_training_reduces_loss(lib):
+    x, t = data(4096, 6)
+    theta0 = M.init_params(7).astype(np.float32)
+    loss0, _ = M.loss_and_grad(theta0.astype(np.float64), x, t)
+    theta, curve = lib.cdwac_mlp_train(theta0, x, t, epochs=40, batch=128, lr=3e-3, seed=1)
+    loss1, _ = M.loss_and_grad(theta.astype(np.float64), x.astype(np.float32).astype(np.float64), t)
+    assert curve[-1] < 0.2 * curve[0]
+    assert loss1 < 0.1 * loss0
+
+
+def test_trained_seed_gain_on_held_out_system(lib):
+    """Same QP energies (<= 1 meV) with and without the seed; report evaluations."""
+    assert os.path.exists(MODEL), "seed_model.npz missing (python -m paper_2305_15955_amd.seed_train)"
+    mdl = np.load(MODEL)
+    lib.cdwac_mlp_set_model(mdl["theta"], mdl["mu"], mdl["sd"], float(mdl["out_mu"]), float(mdl["out_sd"]))
+    case = cases.workload("acene_nmo600")
+    s = case.system
+    sysc, keep = lib.make_system(s)
+    res = {}
+    for mlp in (False, True):
+        prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                    prec="p64", use_mlp_seed=mlp, mlp_accept=1.0e-3 / synth.HARTREE_EV)
+        lib.cdwac_prepare(sysc, prm)
+        res[mlp] = lib.cdwac_qp(s.n_states)
+    d = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(res[False], res[True])]
+    ev0 = np.mean([o["n_evals"] for o in res[False]])
+    ev1 = np.mean([o["n_evals"] for o in res[True]])
+    acc = np.mean([(o["flags"] & 4) != 0 for o in res[True]])
+    print(f"seed: mean evaluations {ev0:.1f} -> {ev1:.1f}, accepted {acc:.2f}, max |dQP| {max(d):.4f} meV")
+    assert max(d) <= 1.0

@@ -329,3 +329,12 @@ def test_fit_range_covers_nonzero_f():
     for om in np.linspace(lo, hi, 101):
         nz = np.nonzero(R.occupation_factor(s.eps, ef, om))[0]
         assert np.all((nz >= m0) & (nz < m1))
+
+
+def test_polarizability_entries_match_full_matrix():
+    s = tiny()
+    pairs = [(0, 0), (3, 1), (6, 6), (2, 5)]
+    for z in (0.4j, 1.1 + 1e-3j):
+        full = R.polarizability(s.o_ia, s.eps, s.n_occ, z, s.spin)
+        ent = R.polarizability_entries(s.o_ia, s.eps, s.n_occ, z, s.spin, pairs)
+        np.testing.assert_allclose(ent, [full[p, q] for p, q in pairs], rtol=1e-13)
