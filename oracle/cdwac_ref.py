@@ -30,8 +30,10 @@ notes of the repository):
 * the QP equation (Eq. qp_eq) is solved by secant from omega_0 = eps_n and one
   fixed-point step; if an iterate leaves the window, the iteration does not
   converge or Z is outside (0, 1], the window is scanned, every upward sign
-  change with |f| < 0.1 Ha on both sides is bisected, and the root with the
-  largest Z (then the one nearest eps_n) is kept.
+  change with |f| < 0.1 Ha on both sides is bisected to 1e-12 Ha, candidates
+  with |f| > 1e-8 Ha at the final midpoint (a jump across a pole, not a zero)
+  are dropped, and the root with the largest Z (then the one nearest eps_n)
+  is kept.
 """
 from __future__ import annotations
 
@@ -45,6 +47,7 @@ QP_SCAN_FMAX = 0.1        # Ha, |f| bound on both sides of an accepted sign chan
 QP_BISECT_TOL = 1e-12     # Ha
 QP_Z_STEP = 1e-4          # Ha, central difference for Z
 QP_F_TOL = 1e-9           # Ha, |f| bound for secant convergence
+QP_ROOT_FTOL = 1e-8       # Ha, |f| bound at a bisected fallback root
 
 FLAG_NOROOT = 1
 FLAG_FALLBACK = 2
@@ -321,6 +324,8 @@ def qp_solve(f: Callable[[float], float], e_n: float, lo: float, hi: float,
             else:
                 b = c
         root = 0.5 * (a + b)
+        if not abs(fe(root)) <= QP_ROOT_FTOL:
+            continue      # a jump across a (near-)pole, not a zero of f
         z = z_factor(root)
         key = (z, -abs(root - e_n))
         if best is None or key > best[0]:

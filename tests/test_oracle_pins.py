@@ -338,3 +338,16 @@ def test_polarizability_entries_match_full_matrix():
         full = R.polarizability(s.o_ia, s.eps, s.n_occ, z, s.spin)
         ent = R.polarizability_entries(s.o_ia, s.eps, s.n_occ, z, s.spin, pairs)
         np.testing.assert_allclose(ent, [full[p, q] for p, q in pairs], rtol=1e-13)
+
+
+def test_qp_fallback_rejects_steep_pole_crossing():
+    """A sign change across a pole is not a root: f = d + 1e-6/d, d = x - x0, has
+    no zero but changes sign upward at x0."""
+    x0 = 0.30037
+    f = lambda x: (x - x0) + 1e-6 / (x - x0)
+    qp, z, nev, flags = R.qp_solve(f, 0.3, 0.25, 0.35)
+    assert flags & R.FLAG_NOROOT and math.isnan(qp)
+    # a smooth root beside a touching (non-crossing) feature is still found
+    g = lambda x: (x - 0.33) * (x - x0) ** 2 / ((x - x0) ** 2 + 1e-6)
+    qp, z, nev, flags = R.qp_solve(g, 0.3, 0.25, 0.35)
+    assert abs(qp - 0.33) < 1e-10
