@@ -115,7 +115,7 @@ def main():
 
     def params(prec, mlp):
         return lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec=prec,
-                               pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4)
+                               pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4 / synth.HARTREE_EV)
 
     sysc, keep = lib.make_system(s, o_ia_dev=o_ia, o_nm_dev=o_nm)
     lib.cdwac_set_timing(True)
@@ -156,8 +156,15 @@ def main():
     pi_s = stages["polarizability"] * 1e-3
     achieved = flops / pi_s / 1e12
     peak = PEAK[args.prec] / 1e12
-    npad = int(math.ceil(s.n_aux / 128.0) * 128)
-    issued = flops * PRODUCTS[args.prec] * (npad * (npad + 128) / 2) / (s.n_aux * (s.n_aux + 1) / 2)
+    if args.prec == "p64":
+        npad = int(math.ceil(s.n_aux / 256.0) * 256)
+        nt = npad // 64
+        tile_elems = nt * (nt + 1) // 2 * 64 * 64
+    else:
+        npad = int(math.ceil(s.n_aux / 256.0) * 256)
+        tile_elems = sum(min(2 * i + 2, npad // 128) for i in range(npad // 256)) * 256 * 128
+    kpad = int(math.ceil(k_dim / 32.0) * 32)
+    issued = float(n_f) * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
     res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                        "frac": achieved / peak, "traffic": None,
                        "kernel": "k_pi_split" if args.prec != "p64" else "k_pi_f64",

@@ -180,11 +180,12 @@ int cdwac_pade_fit_eval(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const doub
 int cdwac_set_timing(cdwac_ctx *ctx, int on);
 
 /* Milliseconds of the stages of the last cdwac_prepare / cdwac_qp with timing
- * on: [0] staging (weights, operand split), [1] polarizability kernel,
- * [2] sweep inversion, [3] Lambda finalisation, [4] W contraction and
- * reduction, [5] exchange and Pade fits, [6] QP kernel.  Writes min(n, 7)
- * values; stages not run are 0. */
-#define CDWAC_N_STAGES 7
+ * on: [0] staging (weights, operand split), [1] polarizability contraction
+ * kernels only, [2] sweep inversion, [3] Lambda finalisation, [4] W
+ * contraction and reduction, [5] exchange and Pade fits, [6] QP kernel,
+ * [7] prescaling of the polarizability operand (16-bit modes).  Writes
+ * min(n, 8) values; stages not run are 0. */
+#define CDWAC_N_STAGES 8
 int cdwac_get_timing(const cdwac_ctx *ctx, double *ms, int32_t n);
 
 /* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------

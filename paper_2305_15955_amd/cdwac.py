@@ -316,7 +316,7 @@ class Cdwac:
         return o[..., 0] + 1j * o[..., 1], nt.cpu().numpy()
 
     STAGES = ("staging", "polarizability", "sweep_inversion", "lambda_finalize", "w_contraction",
-              "exchange_and_fits", "qp")
+              "exchange_and_fits", "qp", "prescale")
 
     def cdwac_set_timing(self, on: bool = True):
         _check(self.ctx, self.lib.cdwac_set_timing(self.ctx, int(bool(on))))

@@ -19,6 +19,10 @@ using namespace cdwac;
 
 namespace {
 
+// Device memory for the prescaled polarizability operands (batched over the
+// weight vectors so that large systems stay within a fixed budget).
+constexpr size_t kPrescaleBudget = (size_t)48 << 30;
+
 // Fit ranges are widened by the Z-factor step of the root search so that
 // every self-energy evaluation of the solver finds a Pade model.
 constexpr double kFitMargin = 1e-4;
@@ -30,14 +34,15 @@ struct Region {
 struct Plan {
     // sizes
     int n_mo, n_occ, n_virt, n_aux, S, n_freq, n_im, n_re, n_pts, n_f, prec;
-    int npad, cpad, cfpad, ni, n_fit, nblk;
+    int npad, cpad, cfpad, ni, n_fit, nblk, nb, n_tpi, n_tw, n_twf;
     int64_t K, kpad;
     // persistent regions
     Region eps, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
         fit_m, w_im, w_re, coef, node, nterm, qpout, err;
     // transient regions (prepare only)
     Region zr, zi, part, idflag, amax, sf, cw, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
-        bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w;
+        bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w, x32, yh, yl, t_pi, t_w,
+        t_wf;
     size_t total = 0;
 };
 
@@ -78,11 +83,15 @@ struct cdwac_ctx {
     // MLP scratch
     void* mlp_scratch = nullptr;
     size_t mlp_scratch_bytes = 0;
-    // stage timing: events ev[i] .. ev[i+1] bracket stage i of prepare; qp uses its own pair
+    // stage timing: segments of kernels bracketed by event pairs on the stream
     bool timing = false;
-    hipEvent_t ev[CDWAC_N_STAGES + 1] = {};
-    hipEvent_t ev_qp[2] = {};
-    bool events_made = false;
+    struct Seg {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Seg> segs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
     double stage_ms[CDWAC_N_STAGES] = {};
 };
 
@@ -197,7 +206,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     P.prec = p->prec;
     P.K = (int64_t)P.n_occ * P.n_virt;
     P.kpad = round_up(P.K, 32);
-    P.npad = (int)round_up(P.n_aux, kPad);
+    P.npad = (int)round_up(P.n_aux, kGemmRows);
     P.nblk = P.npad / kNb;
     P.cpad = (int)round_up((int64_t)P.S * P.n_mo, kPad);
     P.ni = w_partial_blocks(P.prec, P.npad);
@@ -261,6 +270,18 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     } else {
         add(P, P.xh, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
         add(P, P.xl, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
+        add(P, P.x32, sizeof(float) * (size_t)P.npad * P.kpad);
+        // prescaled operands X diag(c_f) for a batch of nb weight vectors
+        const size_t per_f = sizeof(uint16_t) * (size_t)P.npad * P.kpad;
+        P.nb = (int)std::max<size_t>(1, std::min<size_t>(P.n_f, kPrescaleBudget / (2 * per_f)));
+        add(P, P.yh, per_f * P.nb);
+        add(P, P.yl, per_f * P.nb);
+        P.n_tpi = (int)pi_tiles(P.npad).size();
+        P.n_tw = (int)w_tiles(P.npad, P.cpad).size();
+        P.n_twf = (int)w_tiles(P.npad, P.cfpad).size();
+        add(P, P.t_pi, sizeof(int2) * P.n_tpi);
+        add(P, P.t_w, sizeof(int2) * P.n_tw);
+        add(P, P.t_wf, sizeof(int2) * P.n_twf);
     }
     add(P, P.E, sizeof(double) * (size_t)P.n_f * n2);
     add(P, P.dinv_r, sizeof(double) * (size_t)std::max(P.n_freq, 1) * blk);
@@ -333,18 +354,44 @@ int upload(cdwac_ctx* ctx, T* dst, const T* src, size_t n) {
         if (r_ != CDWAC_OK) return r_; \
     } while (0)
 
-int make_events(cdwac_ctx* ctx) {
-    if (ctx->events_made) return CDWAC_OK;
-    for (auto& e : ctx->ev) HIPCK(hipEventCreate(&e));
-    for (auto& e : ctx->ev_qp) HIPCK(hipEventCreate(&e));
-    ctx->events_made = true;
+// Takes an event from the context's pool (handles are copied out: the pool
+// vector may reallocate when it grows).
+int next_event(cdwac_ctx* ctx, hipEvent_t* out) {
+    if (ctx->pool_used == ctx->pool.size()) {
+        hipEvent_t e;
+        HIPCK(hipEventCreate(&e));
+        ctx->pool.push_back(e);
+    }
+    *out = ctx->pool[ctx->pool_used++];
     return CDWAC_OK;
 }
 
-// Records the boundary before stage i (i = CDWAC_N_STAGES - 1 closes the last prepare stage).
-int mark(cdwac_ctx* ctx, int i) {
+// Opens a timed segment of `stage` (closed by seg_end) when timing is on.
+int seg_begin(cdwac_ctx* ctx, int stage) {
     if (!ctx->timing) return CDWAC_OK;
-    HIPCK(hipEventRecord(ctx->ev[i], ctx->stream));
+    hipEvent_t a, b;
+    TRY(next_event(ctx, &a));
+    TRY(next_event(ctx, &b));
+    HIPCK(hipEventRecord(a, ctx->stream));
+    ctx->segs.push_back({stage, a, b});
+    return CDWAC_OK;
+}
+
+int seg_end(cdwac_ctx* ctx) {
+    if (!ctx->timing) return CDWAC_OK;
+    HIPCK(hipEventRecord(ctx->segs.back().b, ctx->stream));
+    return CDWAC_OK;
+}
+
+// After the stream has synchronised: adds every segment to its stage total.
+int seg_collect(cdwac_ctx* ctx) {
+    for (auto& g : ctx->segs) {
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, g.a, g.b));
+        ctx->stage_ms[g.stage] += ms;
+    }
+    ctx->segs.clear();
+    ctx->pool_used = 0;
     return CDWAC_OK;
 }
 
@@ -411,10 +458,7 @@ void cdwac_ctx_destroy(cdwac_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ws_own) (void)hipFree(ctx->ws_own);
-    if (ctx->events_made) {
-        for (auto& e : ctx->ev) (void)hipEventDestroy(e);
-        for (auto& e : ctx->ev_qp) (void)hipEventDestroy(e);
-    }
+    for (auto& e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
     if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
     delete ctx;
@@ -507,11 +551,12 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     TRY(upload(ctx, at<int>(ctx, P.idflag), idf.data(), P.n_f));
     int* err = at<int>(ctx, P.err);
     HIPCK(hipMemsetAsync(err, 0, sizeof(int) * 4, st));
-    if (ctx->timing) TRY(make_events(ctx));
     for (double& x : ctx->stage_ms) x = 0.0;
+    ctx->segs.clear();
+    ctx->pool_used = 0;
 
     // (a0) staging: weights, operand maxima and scales, the O^{ia} operand
-    TRY(mark(ctx, 0));
+    TRY(seg_begin(ctx, 0));
     const int et = prec_elem(P.prec);
     uint32_t* amax = at<uint32_t>(ctx, P.amax);
     double* sf = at<double>(ctx, P.sf);
@@ -526,40 +571,61 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
                    f64 ? at<double>(ctx, P.cw) : nullptr, f64 ? nullptr : at<float>(ctx, P.cw), amax + 2);
     LAUNCHCK();
     if (f64) {
-        launch_split_pad(st, 0, sys->o_ia, P.K, P.n_aux, P.K, nullptr, nullptr, nullptr, at<double>(ctx, P.x64),
-                         P.npad, P.kpad);
+        launch_pad_f64(st, sys->o_ia, P.K, P.n_aux, P.K, at<double>(ctx, P.x64), P.npad, P.kpad);
     } else {
         launch_scales_pi(st, amax, P.n_f, sf);
-        launch_scale_weights(st, at<float>(ctx, P.cw), P.kpad, P.n_f, sf + 2);
-        launch_split_pad(st, et, sys->o_ia, P.K, P.n_aux, P.K, sf, at<uint16_t>(ctx, P.xh), at<uint16_t>(ctx, P.xl),
-                         nullptr, P.npad, P.kpad);
+        launch_split_panel(st, et, sys->o_ia, 0, 1, P.K, P.n_aux, P.K, sf, at<uint16_t>(ctx, P.xh),
+                           at<uint16_t>(ctx, P.xl), at<float>(ctx, P.x32), P.npad, P.kpad);
+        std::vector<int2> tp = pi_tiles(P.npad), tw = w_tiles(P.npad, P.cpad), twf = w_tiles(P.npad, P.cfpad);
+        TRY(upload(ctx, at<int2>(ctx, P.t_pi), tp.data(), tp.size()));
+        TRY(upload(ctx, at<int2>(ctx, P.t_w), tw.data(), tw.size()));
+        TRY(upload(ctx, at<int2>(ctx, P.t_wf), twf.data(), twf.size()));
     }
     LAUNCHCK();
+    TRY(seg_end(ctx));
     // (a1) eps_f = I - Pi_f for every weight vector
-    TRY(mark(ctx, 1));
-    launch_pi(st, P.prec, P.npad, P.kpad, P.n_f, f64 ? at<double>(ctx, P.x64) : nullptr,
-              f64 ? nullptr : at<uint16_t>(ctx, P.xh), f64 ? nullptr : at<uint16_t>(ctx, P.xl),
-              f64 ? at<double>(ctx, P.cw) : nullptr, f64 ? nullptr : at<float>(ctx, P.cw), pi_unscale,
-              at<int>(ctx, P.idflag), at<double>(ctx, P.E));
-    LAUNCHCK();
+    if (f64) {
+        TRY(seg_begin(ctx, 1));
+        launch_pi_f64(st, P.npad, P.kpad, P.n_f, at<double>(ctx, P.x64), at<double>(ctx, P.cw), at<int>(ctx, P.idflag),
+                      at<double>(ctx, P.E));
+        LAUNCHCK();
+        TRY(seg_end(ctx));
+    } else {
+        for (int f0 = 0; f0 < P.n_f; f0 += P.nb) {
+            const int nfb = std::min(P.nb, P.n_f - f0);
+            TRY(seg_begin(ctx, 7));
+            launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, f0, nfb,
+                            at<uint16_t>(ctx, P.yh), at<uint16_t>(ctx, P.yl));
+            LAUNCHCK();
+            TRY(seg_end(ctx));
+            TRY(seg_begin(ctx, 1));
+            launch_pi_gemm(st, P.prec, P.npad, P.kpad, f0, nfb, at<uint16_t>(ctx, P.xh), at<uint16_t>(ctx, P.xl),
+                           at<uint16_t>(ctx, P.yh), at<uint16_t>(ctx, P.yl), at<int2>(ctx, P.t_pi), P.n_tpi, pi_unscale,
+                           at<int>(ctx, P.idflag), at<double>(ctx, P.E));
+            LAUNCHCK();
+            TRY(seg_end(ctx));
+        }
+    }
     // (a2) eps^-1 by blocked sweeps, Lambda = eps^-1 - I
-    TRY(mark(ctx, 2));
+    TRY(seg_begin(ctx, 2));
     launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_freq, P.n_re, P.n_freq, at<double>(ctx, P.dinv_r),
                  at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
                  at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
     LAUNCHCK();
-    TRY(mark(ctx, 3));
+    TRY(seg_end(ctx));
+    TRY(seg_begin(ctx, 3));
     launch_finalize_lambda(st, at<double>(ctx, P.E), P.npad, P.n_f, at<int>(ctx, P.idflag),
                            f64 ? nullptr : amax + 2 + P.n_f);
     LAUNCHCK();
     if (!f64) {
         launch_scales_w(st, amax + 2 + P.n_f, P.n_f, sf, lam_scale, w_unscale);
-        launch_split_lambda(st, et, at<double>(ctx, P.E), P.npad, P.n_f, lam_scale, at<uint16_t>(ctx, P.lh),
-                            at<uint16_t>(ctx, P.ll));
+        launch_split_panel(st, et, at<double>(ctx, P.E), (int64_t)P.npad * P.npad, P.n_f, P.npad, P.npad, P.npad,
+                           lam_scale, at<uint16_t>(ctx, P.lh), at<uint16_t>(ctx, P.ll), nullptr, P.npad, P.npad);
         LAUNCHCK();
     }
+    TRY(seg_end(ctx));
     // (a3) W^c_nm: all (n, m) at the imaginary nodes, fitted (n, m) at the near-real points
-    TRY(mark(ctx, 4));
+    TRY(seg_begin(ctx, 4));
     const double* bscale = f64 ? nullptr : sf + 1;
     launch_transpose_b(st, et, sys->o_nm, P.S, P.n_aux, P.n_mo, nullptr, P.S * P.n_mo, bscale, at<double>(ctx, P.bt64),
                        f64 ? nullptr : at<uint16_t>(ctx, P.bh), f64 ? nullptr : at<uint16_t>(ctx, P.bl), P.cpad,
@@ -573,21 +639,24 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     }
     launch_w(st, P.prec, P.npad, 0, P.n_freq, at<double>(ctx, P.E), f64 ? nullptr : at<uint16_t>(ctx, P.lh),
              f64 ? nullptr : at<uint16_t>(ctx, P.ll), at<double>(ctx, P.bt64), f64 ? nullptr : at<uint16_t>(ctx, P.bh),
-             f64 ? nullptr : at<uint16_t>(ctx, P.bl), P.cpad, w_unscale, at<double>(ctx, P.partial_im));
+             f64 ? nullptr : at<uint16_t>(ctx, P.bl), P.cpad, f64 ? nullptr : at<int2>(ctx, P.t_w), P.n_tw, w_unscale,
+             at<double>(ctx, P.partial_im));
     LAUNCHCK();
     if (P.n_re > 0 && P.n_fit > 0) {
         launch_w(st, P.prec, P.npad, P.n_freq, 2 * P.n_re, at<double>(ctx, P.E),
                  f64 ? nullptr : at<uint16_t>(ctx, P.lh), f64 ? nullptr : at<uint16_t>(ctx, P.ll),
                  at<double>(ctx, P.bf64), f64 ? nullptr : at<uint16_t>(ctx, P.bfh),
-                 f64 ? nullptr : at<uint16_t>(ctx, P.bfl), P.cfpad, w_unscale, at<double>(ctx, P.partial_re));
+                 f64 ? nullptr : at<uint16_t>(ctx, P.bfl), P.cfpad, f64 ? nullptr : at<int2>(ctx, P.t_wf), P.n_twf,
+                 w_unscale, at<double>(ctx, P.partial_re));
         LAUNCHCK();
     }
     launch_reduce_w(st, at<double>(ctx, P.partial_im), at<double>(ctx, P.partial_re), P.ni, P.cpad, P.cfpad,
                     P.n_freq, P.n_re, P.S * P.n_mo, P.n_re > 0 ? P.n_fit : 0, at<double>(ctx, P.w_im),
                     at<double>(ctx, P.w_re));
     LAUNCHCK();
+    TRY(seg_end(ctx));
     // (a4) Sigma^x and v^xc
-    TRY(mark(ctx, 5));
+    TRY(seg_begin(ctx, 5));
     launch_exchange(st, sys->o_nm, P.S, P.n_aux, P.n_mo, P.n_occ, at<double>(ctx, P.sigx));
     LAUNCHCK();
     if (sys->vxc) TRY(upload(ctx, at<double>(ctx, P.vxc), sys->vxc, P.S));
@@ -604,17 +673,11 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
                           at<double>(ctx, P.coef), at<double>(ctx, P.node), at<int>(ctx, P.nterm));
         LAUNCHCK();
     }
-    TRY(mark(ctx, 6));
+    TRY(seg_end(ctx));
     int herr[4] = {0, 0, 0, 0};
     HIPCK(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
-    if (ctx->timing) {
-        for (int i = 0; i < 6; ++i) {
-            float ms = 0.f;
-            HIPCK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
-            ctx->stage_ms[i] = ms;
-        }
-    }
+    TRY(seg_collect(ctx));
     if (herr[0] & 2) return fail(ctx, CDWAC_EINVAL, "non-finite value in the RI coefficients");
     if (herr[0] & 1) return fail(ctx, CDWAC_ENOTPD, "zero or non-finite pivot while inverting eps = I - Pi");
     ctx->hs = hs;
@@ -633,21 +696,15 @@ int cdwac_qp(cdwac_ctx* ctx, const double* vxc, cdwac_state_out* out) {
     hipStream_t st = ctx->stream;
     if (vxc) TRY(upload(ctx, at<double>(ctx, P.vxc), vxc, P.S));
     QpArgs a = qp_args(ctx);
-    if (ctx->timing) {
-        TRY(make_events(ctx));
-        HIPCK(hipEventRecord(ctx->ev_qp[0], st));
-    }
+    ctx->stage_ms[6] = 0.0;
+    TRY(seg_begin(ctx, 6));
     launch_qp(st, a, at<QpOut>(ctx, P.qpout));
     LAUNCHCK();
-    if (ctx->timing) HIPCK(hipEventRecord(ctx->ev_qp[1], st));
+    TRY(seg_end(ctx));
     static_assert(sizeof(QpOut) == sizeof(cdwac_state_out), "output layout");
     HIPCK(hipMemcpyAsync(out, at<QpOut>(ctx, P.qpout), sizeof(QpOut) * P.S, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
-    if (ctx->timing) {
-        float ms = 0.f;
-        HIPCK(hipEventElapsedTime(&ms, ctx->ev_qp[0], ctx->ev_qp[1]));
-        ctx->stage_ms[6] = ms;
-    }
+    TRY(seg_collect(ctx));
     for (int j = 0; j < P.S; ++j)
         if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
     return CDWAC_OK;
@@ -718,7 +775,7 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
     hipStream_t st = ctx->stream;
     const int n_virt = sys->n_mo - sys->n_occ;
     const int64_t K = (int64_t)sys->n_occ * n_virt, kpad = round_up(K, 32);
-    const int npad = (int)round_up(sys->n_aux, kPad);
+    const int npad = (int)round_up(sys->n_aux, kGemmRows);
     const int nf = 2 * n_z;
     const bool f64 = prec == CDWAC_P64;
     std::vector<double> zr(nf), zi(nf);
@@ -738,8 +795,10 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
     size_t o_eps = take(sizeof(double) * sys->n_mo), o_zr = take(sizeof(double) * nf), o_zi = take(sizeof(double) * nf),
            o_part = take(sizeof(int) * nf), o_id = take(sizeof(int) * nf), o_err = take(sizeof(int) * 4),
            o_amax = take(sizeof(uint32_t) * (2 + 2 * (size_t)nf)), o_sf = take(sizeof(double) * (2 + 4 * (size_t)nf)),
-           o_cw = take((f64 ? 8 : 4) * (size_t)nf * kpad), o_x = take((f64 ? 8 : 4) * (size_t)npad * kpad),
-           o_E = take(sizeof(double) * (size_t)nf * npad * npad);
+           o_cw = take((f64 ? 8 : 4) * (size_t)nf * kpad), o_x = take(8 * (size_t)npad * kpad),
+           o_y = take(f64 ? 0 : 4 * (size_t)nf * npad * kpad), o_E = take(sizeof(double) * (size_t)nf * npad * npad);
+    const std::vector<int2> tiles = f64 ? std::vector<int2>() : pi_tiles(npad);
+    size_t o_t = take(sizeof(int2) * std::max<size_t>(1, tiles.size()));
     char* buf = nullptr;
     if (hipMalloc(&buf, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -766,17 +825,25 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
                        f64 ? nullptr : (float*)(buf + o_cw), amax + 2);
         uint16_t* xh = (uint16_t*)(buf + o_x);
         uint16_t* xl = xh + (size_t)npad * kpad;
+        float* x32 = (float*)(xl + (size_t)npad * kpad);
+        uint16_t* yh = (uint16_t*)(buf + o_y);
+        uint16_t* yl = yh + (size_t)nf * npad * kpad;
         if (f64) {
-            launch_split_pad(st, 0, sys->o_ia, K, sys->n_aux, K, nullptr, nullptr, nullptr, (double*)(buf + o_x), npad,
-                             kpad);
+            launch_pad_f64(st, sys->o_ia, K, sys->n_aux, K, (double*)(buf + o_x), npad, kpad);
+            launch_pi_f64(st, npad, kpad, nf, (double*)(buf + o_x), (double*)(buf + o_cw), (int*)(buf + o_id),
+                          (double*)(buf + o_E));
         } else {
+            const int et = prec_elem(prec);
+            if (hipMemcpyAsync(buf + o_t, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st)) {
+                rc = fail(ctx, CDWAC_EHIP, "upload failed");
+                break;
+            }
             launch_scales_pi(st, amax, nf, sf);
-            launch_scale_weights(st, (float*)(buf + o_cw), kpad, nf, sf + 2);
-            launch_split_pad(st, prec_elem(prec), sys->o_ia, K, sys->n_aux, K, sf, xh, xl, nullptr, npad, kpad);
+            launch_split_panel(st, et, sys->o_ia, 0, 1, K, sys->n_aux, K, sf, xh, xl, x32, npad, kpad);
+            launch_prescale(st, et, x32, npad, kpad, (float*)(buf + o_cw), sf + 2, 0, nf, yh, yl);
+            launch_pi_gemm(st, prec, npad, kpad, 0, nf, xh, xl, yh, yl, (int2*)(buf + o_t), (int)tiles.size(),
+                           sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));
         }
-        launch_pi(st, prec, npad, kpad, nf, f64 ? (double*)(buf + o_x) : nullptr, f64 ? nullptr : xh,
-                  f64 ? nullptr : xl, f64 ? (double*)(buf + o_cw) : nullptr, f64 ? nullptr : (float*)(buf + o_cw),
-                  sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));
         if (hipGetLastError() != hipSuccess) {
             rc = fail(ctx, CDWAC_EHIP, "kernel launch failed");
             break;

@@ -26,6 +26,18 @@ constexpr int kMaxPade = 64;
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// ---- panel layout of a 16-bit contraction operand ---------------------------
+// Rows are padded to a multiple of 64 and K to a multiple of 32.  Each block
+// of 64 rows is stored contiguously as [K / 8][64 rows][8], so the eight
+// elements k .. k+7 (k % 8 == 0) of one row form one 16-byte word and the 64
+// rows of a block at one k-group are 1 KiB of consecutive memory: one
+// wave-wide 16-byte load fetches whole cache lines and lands in LDS as
+// [k-group][row], the order the matrix-core fragments are read in.  Row block
+// b starts at element b * 64 * K, as it would in row-major order.
+__host__ __device__ inline int64_t panel_off(int64_t p, int64_t k, int64_t K) {
+    return (((p >> 6) * (K >> 3) + (k >> 3)) * 64 + (p & 63)) * 8 + (k & 7);
+}
+
 // ---- bf16 split: x ~= hi + lo with hi = rn(x), lo = rn(x - hi) ------------
 __device__ inline uint16_t bf16_bits(float x) {
     __bf16 h = (__bf16)x;                 // round to nearest even

@@ -15,6 +15,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <vector>
 
 namespace cdwac {
 
@@ -175,60 +176,58 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 
 
 // ============================================================================
-// Split 16-bit MFMA tile machinery: 128 x 128 output tile, 4 waves of 64 x 64
-// (2 x 2 blocks of 32 x 32 x 16), K chunks of 32 staged in LDS as
-// [k-group of 8][row] so that each lane's 16-byte fragment read is contiguous.
+// 16-bit split MFMA contraction (v_mfma_f32_32x32x16_{bf16,f16}).
+//
+// One workgroup of 8 waves computes a GM x GN = 256 x 128 tile of A B^T with
+// both operands stored as hi/lo planes in the panel layout of panel_off (K is
+// the leading dimension lda = ldb), so each wave-wide load of one 64-row block
+// at one k-group reads 1 KiB of consecutive memory.  Each wave
+// owns 64 x 64 (2 x 2 MFMA blocks).  K advances in chunks of 32 through a
+// 3-stage LDS ring filled by direct global-to-LDS loads (no register
+// staging): chunk i+2 is in flight while chunk i is multiplied.  LDS layout
+// per stage: [plane][k-group of 8][row] x 16 bytes, so every lane's fragment
+// read is one contiguous 16-byte word.  Products hi*hi + hi*lo + lo*hi are
+// accumulated in FP32 and flushed into FP64 every kFlushChunks chunks.
+// Tiles come from a host-built list ordered in 2-D blocks, so the workgroups
+// an XCD runs together share operand panels in its L2.
 // ============================================================================
 
-constexpr int B_BT = 128, B_KC = 32, kFlushChunks = 64;   // flush every 2048 k
+constexpr int GM = 256, GN = 128, GK = 32, NST = 3, kFlushChunks = 64;
+constexpr int kGemmThreads = 512;
+constexpr int A_STAGE = 2 * 4 * GM;   // uint4 slots of A per stage
+constexpr int B_STAGE = 2 * 4 * GN;
+constexpr int STAGE = A_STAGE + B_STAGE;
 
-struct SplitStage {
-    uint4 ah[4][B_BT], al[4][B_BT], bh[4][B_BT], bl[4][B_BT];
-};
+typedef __attribute__((address_space(3))) void lds_void;
 
-struct SplitFrag {
-    uint4 ah[2], al[2], bh[2], bl[2];
-};
-
-__device__ inline uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
-
-// Rescale the B operand by per-k weights and split again: y = (hi + lo) * c.
-template <int ET>
-__device__ inline void reweight(uint4& h, uint4& l, const float* c) {
-    uint32_t hw[4] = {h.x, h.y, h.z, h.w}, lw[4] = {l.x, l.y, l.z, l.w};
-    uint32_t oh[4], ol[4];
+// Issues this wave's share (6 of 48 row-block loads) of chunk k0 into stage st.
+__device__ inline void gemm_issue(uint4* lds, int st, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
+                                  int64_t lda, const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl,
+                                  int64_t ldb, int64_t k0, int w, int lane) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        uint32_t rh = 0, rl = 0;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            uint16_t bh = (uint16_t)(hw[q] >> (16 * e)), bl = (uint16_t)(lw[q] >> (16 * e));
-            float y = (Elem<ET>::val(bh) + Elem<ET>::val(bl)) * c[2 * q + e];
-            uint16_t yh = Elem<ET>::bits(y);
-            uint16_t yl = Elem<ET>::bits(y - Elem<ET>::val(yh));
-            rh |= (uint32_t)yh << (16 * e);
-            rl |= (uint32_t)yl << (16 * e);
+    for (int q = 0; q < 6; ++q) {
+        const int u = w * 6 + q;
+        const uint16_t* g;
+        int slot;
+        if (u < 32) {   // A: plane u/16, k-group (u/4)%4, row block u%4
+            const int pl = u >> 4, kg = (u >> 2) & 3, rb = u & 3;
+            g = (pl ? al : ah) + (int64_t)rb * 64 * lda + (k0 + kg * 8) * 64 + lane * 8;
+            slot = (pl * 4 + kg) * GM + rb * 64;
+        } else {        // B: plane v/8, k-group (v/2)%4, row block v%2
+            const int v = u - 32;
+            const int pl = v >> 3, kg = (v >> 1) & 3, rb = v & 1;
+            g = (pl ? bl : bh) + (int64_t)rb * 64 * ldb + (k0 + kg * 8) * 64 + lane * 8;
+            slot = A_STAGE + (pl * 4 + kg) * GN + rb * 64;
         }
-        oh[q] = rh;
-        ol[q] = rl;
-    }
-    h = make_uint4(oh[0], oh[1], oh[2], oh[3]);
-    l = make_uint4(ol[0], ol[1], ol[2], ol[3]);
-}
-
-__device__ inline void split_store_stage(SplitStage& st, const SplitFrag& fr, int row, int kg0) {
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        st.ah[kg0 + g][row] = fr.ah[g];
-        st.al[kg0 + g][row] = fr.al[g];
-        st.bh[kg0 + g][row] = fr.bh[g];
-        st.bl[kg0 + g][row] = fr.bl[g];
+        __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(lds + st * STAGE + slot), 16, 0, 0);
     }
 }
 
 template <int ET, bool SPLIT>
-__device__ inline void split_chunk(const SplitStage& st, int wr, int wc, int lane, v16f (&acc)[2][2]) {
+__device__ inline void gemm_chunk(const uint4* lds, int st, int wr, int wc, int lane, v16f (&acc)[2][2]) {
     typedef typename Elem<ET>::vec V;
+    const uint4* sa = lds + st * STAGE;
+    const uint4* sb = sa + A_STAGE;
     const int r = lane & 31, hg = lane >> 5;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -236,11 +235,11 @@ __device__ inline void split_chunk(const SplitStage& st, int wr, int wc, int lan
         V ahv[2], alv[2], bhv[2], blv[2];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            ahv[b] = __builtin_bit_cast(V, st.ah[kg][wr * 64 + b * 32 + r]);
-            bhv[b] = __builtin_bit_cast(V, st.bh[kg][wc * 64 + b * 32 + r]);
+            ahv[b] = __builtin_bit_cast(V, sa[kg * GM + wr * 64 + b * 32 + r]);
+            bhv[b] = __builtin_bit_cast(V, sb[kg * GN + wc * 64 + b * 32 + r]);
             if (SPLIT) {
-                alv[b] = __builtin_bit_cast(V, st.al[kg][wr * 64 + b * 32 + r]);
-                blv[b] = __builtin_bit_cast(V, st.bl[kg][wc * 64 + b * 32 + r]);
+                alv[b] = __builtin_bit_cast(V, sa[(4 + kg) * GM + wr * 64 + b * 32 + r]);
+                blv[b] = __builtin_bit_cast(V, sb[(4 + kg) * GN + wc * 64 + b * 32 + r]);
             }
         }
 #pragma unroll
@@ -256,97 +255,79 @@ __device__ inline void split_chunk(const SplitStage& st, int wr, int wc, int lan
     }
 }
 
-// accd = A[rows] * (B[rows] diag(cw))^T over K (multiple of 32), FP32 products
-// flushed into the FP64 accumulators every kFlushChunks chunks.
-template <int ET, bool SPLIT, bool WEIGHTED>
-__device__ inline void split_tile_product(const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
-                                          int64_t lda, const uint16_t* __restrict__ bh,
-                                          const uint16_t* __restrict__ bl, int64_t ldb,
-                                          const float* __restrict__ cw, int64_t K, SplitStage (&st)[2],
-                                          double (&accd)[2][2][16]) {
+// s_waitcnt immediates (gfx9 encoding, other counters left open).
+constexpr int kWaitVm6 = (15 << 8) | (7 << 4) | 6;
+constexpr int kWaitVm0 = (15 << 8) | (7 << 4) | 0;
+
+// accd = A[rows a0..a0+GM) * B[rows b0..b0+GN)^T over K (multiple of GK).
+template <int ET, bool SPLIT>
+__device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
+                                 int64_t lda, const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl,
+                                 int64_t ldb, int64_t K, double (&accd)[2][2][16]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
-    const int row = t >> 1, kg0 = (t & 1) * 2;
-    const uint16_t* pah = ah + (int64_t)row * lda + kg0 * 8;
-    const uint16_t* pal = al + (int64_t)row * lda + kg0 * 8;
-    const uint16_t* pbh = bh + (int64_t)row * ldb + kg0 * 8;
-    const uint16_t* pbl = bl + (int64_t)row * ldb + kg0 * 8;
-    const float* pc = WEIGHTED ? cw + kg0 * 8 : nullptr;
-    const int64_t nk = K / B_KC;
-    SplitFrag fr;
-    auto load = [&](int64_t k0) {
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            fr.ah[g] = ld16(pah + k0 + 8 * g);
-            fr.bh[g] = ld16(pbh + k0 + 8 * g);
-            if (SPLIT || WEIGHTED) {
-                fr.al[g] = ld16(pal + k0 + 8 * g);
-                fr.bl[g] = ld16(pbl + k0 + 8 * g);
-            }
-        }
-        if (WEIGHTED) {
-            float c[16];
-            const float4* q4 = reinterpret_cast<const float4*>(pc + k0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float4 v = q4[q];
-                c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
-            }
-            reweight<ET>(fr.bh[0], fr.bl[0], c);
-            reweight<ET>(fr.bh[1], fr.bl[1], c + 8);
-        }
-    };
-    v16f acc[2][2];
+    const int64_t nk = K / GK;
+    // two-level FP32 sums: acc holds the current kFlushChunks chunks, tot the
+    // flushed ones, so each rounding is relative to a partial sum of at most
+    // 2048 terms or to the running total once per flush
+    v16f acc[2][2], tot[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             acc[bi][bj] = v16f{};
-#pragma unroll
-            for (int v = 0; v < 16; ++v) accd[bi][bj][v] = 0.0;
+            tot[bi][bj] = v16f{};
         }
-    auto flush = [&]() {
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) accd[bi][bj][v] += (double)acc[bi][bj][v];
-                acc[bi][bj] = v16f{};
-            }
-    };
-    load(0);
-    split_store_stage(st[0], fr, row, kg0);
-    __syncthreads();
+    gemm_issue(lds, 0, ah, al, lda, bh, bl, ldb, 0, w, lane);
+    if (nk > 1) gemm_issue(lds, 1, ah, al, lda, bh, bl, ldb, GK, w, lane);
     for (int64_t i = 0; i < nk; ++i) {
-        const int s = (int)(i & 1);
-        if (i + 1 < nk) load((i + 1) * B_KC);
-        split_chunk<ET, SPLIT>(st[s], wr, wc, lane, acc);
-        if ((i + 1) % kFlushChunks == 0) flush();
-        if (i + 1 < nk) split_store_stage(st[s ^ 1], fr, row, kg0);
+        if (i + 1 < nk) __builtin_amdgcn_s_waitcnt(kWaitVm6);
+        else __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
+        if (i + 2 < nk) gemm_issue(lds, (int)((i + 2) % NST), ah, al, lda, bh, bl, ldb, (i + 2) * GK, w, lane);
+        gemm_chunk<ET, SPLIT>(lds, (int)(i % NST), wr, wc, lane, acc);
+        if ((i + 1) % kFlushChunks == 0 || i + 1 == nk) {
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) {
+                    tot[bi][bj] += acc[bi][bj];
+                    acc[bi][bj] = v16f{};
+                }
+        }
     }
-    flush();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) accd[bi][bj][v] = (double)tot[bi][bj][v];
 }
 
-// eps_f = delta_f I - Pi_f on the lower 128 x 128 tiles; acc * pi_unscale[f] = Pi_f.
+// Row of the output element held by (lane, v) inside a wave's 64 x 64 block bi.
+__device__ inline int out_row(int wr, int bi, int lane, int v) {
+    return wr * 64 + bi * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+// eps_f = delta_f I - Pi_f for the listed tiles of batch f (B = prescaled Y_f).
 template <int ET, bool SPLIT>
-__global__ __launch_bounds__(256) void k_pi_split(const uint16_t* __restrict__ xh,
-                                                  const uint16_t* __restrict__ xl, int64_t kpad,
-                                                  const float* __restrict__ cw,
-                                                  const double* __restrict__ pi_unscale,
-                                                  const int* __restrict__ idflag, double* __restrict__ E,
-                                                  int npad) {
-    __shared__ SplitStage st[2];
-    const int nt = npad / B_BT, T = nt * (nt + 1) / 2;
+__global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __restrict__ xh,
+                                                          const uint16_t* __restrict__ xl,
+                                                          const uint16_t* __restrict__ yh,
+                                                          const uint16_t* __restrict__ yl, int64_t kpad,
+                                                          const int2* __restrict__ tiles, int n_tiles, int f0,
+                                                          const double* __restrict__ pi_unscale,
+                                                          const int* __restrict__ idflag, double* __restrict__ E,
+                                                          int npad) {
+    __shared__ uint4 lds[NST * STAGE];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int f = bid / T;
-    int I, J;
-    lower_tile(bid % T, I, J);
+    const int fb = bid / n_tiles;
+    const int2 tile = tiles[bid % n_tiles];
+    const int I = tile.x, J = tile.y, f = f0 + fb;
     double accd[2][2][16];
-    const int64_t ai = (int64_t)I * B_BT * kpad, bj0 = (int64_t)J * B_BT * kpad;
-    split_tile_product<ET, SPLIT, true>(xh + ai, xl + ai, kpad, xh + bj0, xl + bj0, kpad,
-                                        cw + (int64_t)f * kpad, kpad, st, accd);
+    const int64_t ao = (int64_t)I * GM * kpad;
+    const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GN * kpad;
+    gemm_tile<ET, SPLIT>(lds, xh + ao, xl + ao, kpad, yh + bo, yl + bo, kpad, kpad, accd);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
     const double id = idflag[f] ? 1.0 : 0.0;
     const double us = pi_unscale[f];
@@ -357,98 +338,127 @@ __global__ __launch_bounds__(256) void k_pi_split(const uint16_t* __restrict__ x
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                int P = I * B_BT + wr * 64 + bi * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                int Q = J * B_BT + wc * 64 + bj * 32 + (lane & 31);
+                int P = I * GM + out_row(wr, bi, lane, v);
+                int Q = J * GN + wc * 64 + bj * 32 + (lane & 31);
                 Ef[(int64_t)P * npad + Q] = (P == Q ? id : 0.0) - accd[bi][bj][v] * us;
             }
 }
 
-// partial[f][I][c] = sum_{P in tile I} B[c][P] (Lambda_f B^T)[P][c]; acc * w_unscale[f] = Lambda B^T.
+// partial[fl][I][c] = sum_{P in row block I} B[c][P] (Lambda_f B^T)[P][c]
 template <int ET, bool SPLIT>
-__global__ __launch_bounds__(256) void k_w_split(const uint16_t* __restrict__ lh,
-                                                 const uint16_t* __restrict__ ll, int npad,
-                                                 const uint16_t* __restrict__ bh,
-                                                 const uint16_t* __restrict__ bl,
-                                                 const double* __restrict__ bt64, int cpad, int f0,
-                                                 const double* __restrict__ w_unscale,
-                                                 double* __restrict__ partial) {
-    __shared__ SplitStage st[2];
-    __shared__ double red[2][B_BT];
-    const int ni = npad / B_BT, nc = cpad / B_BT;
+__global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restrict__ lh,
+                                                         const uint16_t* __restrict__ ll, int npad,
+                                                         const uint16_t* __restrict__ bh,
+                                                         const uint16_t* __restrict__ bl,
+                                                         const double* __restrict__ bt64, int cpad,
+                                                         const int2* __restrict__ tiles, int n_tiles, int f0,
+                                                         const double* __restrict__ w_unscale,
+                                                         double* __restrict__ partial) {
+    __shared__ uint4 lds[NST * STAGE];
+    __shared__ double red[4][GN];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int fl = bid / (ni * nc);
-    const int rem = bid % (ni * nc);
-    const int I = rem % ni, J = rem / ni;
-    const int64_t lo = (int64_t)(f0 + fl) * npad * npad + (int64_t)I * B_BT * npad;
-    const int64_t bo = (int64_t)J * B_BT * npad;
+    const int fl = bid / n_tiles;
+    const int2 tile = tiles[bid % n_tiles];
+    const int I = tile.x, J = tile.y;
+    const int ni = npad / GM;
+    const int64_t lo = (int64_t)(f0 + fl) * npad * npad + (int64_t)I * GM * npad;
+    const int64_t bo = (int64_t)J * GN * npad;
     double accd[2][2][16];
-    split_tile_product<ET, SPLIT, false>(lh + lo, ll + lo, npad, bh + bo, bl + bo, npad, nullptr, npad, st, accd);
+    gemm_tile<ET, SPLIT>(lds, lh + lo, ll + lo, npad, bh + bo, bl + bo, npad, npad, accd);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
     const double us = w_unscale[f0 + fl];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-        const int c = J * B_BT + wc * 64 + bj * 32 + (lane & 31);
-        const double* brow = bt64 + (int64_t)c * npad;
+        const int c = J * GN + wc * 64 + bj * 32 + (lane & 31);
+        const double* brow = bt64 + (int64_t)c * npad + I * GM;
         double s = 0.0;
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                int P = I * B_BT + wr * 64 + bi * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                s += brow[P] * accd[bi][bj][v];
-            }
+            for (int v = 0; v < 16; ++v) s += brow[out_row(wr, bi, lane, v)] * accd[bi][bj][v];
         s *= us;
         s += __shfl_xor(s, 32);
         if (lane < 32) red[wr][wc * 64 + bj * 32 + lane] = s;
     }
     __syncthreads();
-    if (threadIdx.x < B_BT) {
-        int c = J * B_BT + threadIdx.x;
-        partial[((int64_t)fl * ni + I) * cpad + c] = red[0][threadIdx.x] + red[1][threadIdx.x];
+    if (threadIdx.x < GN) {
+        int c = J * GN + threadIdx.x;
+        partial[((int64_t)fl * ni + I) * cpad + c] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
     }
 }
 
 // ============================================================================
-// Host launchers
+// Host side: tile lists and launchers
 // ============================================================================
 
-void launch_pi(hipStream_t s, int prec, int npad, int64_t kpad, int n_f, const double* x64, const uint16_t* xh,
-               const uint16_t* xl, const double* cw64, const float* cw32, const double* pi_unscale,
-               const int* idflag, double* E) {
-    if (prec == PREC_P64) {
-        int nt = npad / F_BT, T = nt * (nt + 1) / 2;
-        hipLaunchKernelGGL(k_pi_f64, dim3(T * n_f), dim3(256), 0, s, x64, kpad, cw64, idflag, E, npad, n_f);
-        return;
-    }
-    int nt = npad / B_BT, T = nt * (nt + 1) / 2;
-    dim3 g(T * n_f), b(256);
+// Tiles (I, J) of GM x GN covering the lower triangle of an npad x npad
+// matrix (J <= 2I + 1), in 4 x 8 blocks so that consecutive tiles share
+// operand panels.
+std::vector<int2> pi_tiles(int npad) {
+    std::vector<int2> out;
+    const int nI = npad / GM, nJ = npad / GN;
+    for (int I0 = 0; I0 < nI; I0 += 4)
+        for (int J0 = 0; J0 < nJ; J0 += 8)
+            for (int I = I0; I < std::min(nI, I0 + 4); ++I)
+                for (int J = J0; J < std::min(nJ, J0 + 8); ++J)
+                    if (J <= 2 * I + 1) out.push_back(make_int2(I, J));
+    return out;
+}
+
+// Full ni x nc grid of W tiles in 4 x 8 blocks.
+std::vector<int2> w_tiles(int npad, int cpad) {
+    std::vector<int2> out;
+    const int nI = npad / GM, nJ = cpad / GN;
+    for (int I0 = 0; I0 < nI; I0 += 4)
+        for (int J0 = 0; J0 < nJ; J0 += 8)
+            for (int I = I0; I < std::min(nI, I0 + 4); ++I)
+                for (int J = J0; J < std::min(nJ, J0 + 8); ++J) out.push_back(make_int2(I, J));
+    return out;
+}
+
+void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double* x64, const double* cw64,
+                   const int* idflag, double* E) {
+    int nt = npad / F_BT, T = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_pi_f64, dim3(T * n_f), dim3(256), 0, s, x64, kpad, cw64, idflag, E, npad, n_f);
+}
+
+void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, int f0, int nfb, const uint16_t* xh,
+                    const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* tiles, int n_tiles,
+                    const double* pi_unscale, const int* idflag, double* E) {
+    dim3 g(n_tiles * nfb), b(kGemmThreads);
     if (prec == PREC_B16X3)
-        hipLaunchKernelGGL((k_pi_split<0, true>), g, b, 0, s, xh, xl, kpad, cw32, pi_unscale, idflag, E, npad);
+        hipLaunchKernelGGL((k_pi_gemm<0, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, f0, pi_unscale,
+                           idflag, E, npad);
     else if (prec == PREC_B16)
-        hipLaunchKernelGGL((k_pi_split<0, false>), g, b, 0, s, xh, xl, kpad, cw32, pi_unscale, idflag, E, npad);
+        hipLaunchKernelGGL((k_pi_gemm<0, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, f0, pi_unscale,
+                           idflag, E, npad);
     else
-        hipLaunchKernelGGL((k_pi_split<1, true>), g, b, 0, s, xh, xl, kpad, cw32, pi_unscale, idflag, E, npad);
+        hipLaunchKernelGGL((k_pi_gemm<1, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, f0, pi_unscale,
+                           idflag, E, npad);
 }
 
-int w_partial_blocks(int prec, int npad) { return npad / (prec == PREC_P64 ? F_BT : B_BT); }
+int w_partial_blocks(int prec, int npad) { return npad / (prec == PREC_P64 ? F_BT : GM); }
 
 void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* lam64, const uint16_t* lh,
               const uint16_t* ll, const double* bt64, const uint16_t* bh, const uint16_t* bl, int cpad,
-              const double* w_unscale, double* partial) {
+              const int2* tiles, int n_tiles, const double* w_unscale, double* partial) {
     if (nf <= 0) return;
     if (prec == PREC_P64) {
         int ni = npad / F_BT, nc = cpad / F_BT;
         hipLaunchKernelGGL(k_w_f64, dim3(ni * nc * nf), dim3(256), 0, s, lam64, npad, bt64, cpad, f0, partial);
         return;
     }
-    int ni = npad / B_BT, nc = cpad / B_BT;
-    dim3 g(ni * nc * nf), b(256);
+    dim3 g(n_tiles * nf), b(kGemmThreads);
     if (prec == PREC_B16X3)
-        hipLaunchKernelGGL((k_w_split<0, true>), g, b, 0, s, lh, ll, npad, bh, bl, bt64, cpad, f0, w_unscale, partial);
+        hipLaunchKernelGGL((k_w_gemm<0, true>), g, b, 0, s, lh, ll, npad, bh, bl, bt64, cpad, tiles, n_tiles, f0,
+                           w_unscale, partial);
     else if (prec == PREC_B16)
-        hipLaunchKernelGGL((k_w_split<0, false>), g, b, 0, s, lh, ll, npad, bh, bl, bt64, cpad, f0, w_unscale, partial);
+        hipLaunchKernelGGL((k_w_gemm<0, false>), g, b, 0, s, lh, ll, npad, bh, bl, bt64, cpad, tiles, n_tiles, f0,
+                           w_unscale, partial);
     else
-        hipLaunchKernelGGL((k_w_split<1, true>), g, b, 0, s, lh, ll, npad, bh, bl, bt64, cpad, f0, w_unscale, partial);
+        hipLaunchKernelGGL((k_w_gemm<1, true>), g, b, 0, s, lh, ll, npad, bh, bl, bt64, cpad, tiles, n_tiles, f0,
+                           w_unscale, partial);
 }
 
 }  // namespace cdwac

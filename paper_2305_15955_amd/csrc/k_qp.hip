@@ -9,14 +9,16 @@
 // One workgroup per state; every thread runs the same root-search control
 // flow on block-reduced values.  Root search: secant from eps_n (or from the
 // learned seed) and one fixed-point step; fallback: scan the window at 0.01 Ha,
-// bisect every upward sign change with |f| < 0.1 Ha on both sides and keep the
-// root of largest Z (then the one nearest eps_n).
+// bisect every upward sign change with |f| < 0.1 Ha on both sides, drop a
+// candidate whose |f| at the final midpoint exceeds 1e-8 Ha (a jump across a
+// pole), and keep the root of largest Z (then the one nearest eps_n).
 #include "common.h"
 #include "kernels.h"
 
 namespace cdwac {
 
-constexpr double kScanStep = 0.01, kScanFmax = 0.1, kBisectTol = 1e-12, kZStep = 1e-4, kFTol = 1e-9;
+constexpr double kScanStep = 0.01, kScanFmax = 0.1, kBisectTol = 1e-12, kZStep = 1e-4, kFTol = 1e-9,
+                 kRootFTol = 1e-8;
 constexpr int kQpThreads = 256, kMaxFreq = 512;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -216,13 +218,15 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_solve(QpArgs A, QpOut* __rest
                     else b = c;
                 }
                 double r = 0.5 * (a + b);
-                double z = z_factor(r);
-                double d = -fabs(r - e_n);
-                if (!have || z > best_z || (z == best_z && d > best_d)) {
-                    have = true;
-                    best_z = z;
-                    best_d = d;
-                    best_r = r;
+                if (fabs(f(r)) <= kRootFTol) {   // else a jump across a (near-)pole
+                    double z = z_factor(r);
+                    double d = -fabs(r - e_n);
+                    if (!have || z > best_z || (z == best_z && d > best_d)) {
+                        have = true;
+                        best_z = z;
+                        best_d = d;
+                        best_r = r;
+                    }
                 }
             }
             xa = xb;

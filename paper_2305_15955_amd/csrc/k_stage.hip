@@ -84,7 +84,7 @@ __global__ void k_weights(const double* __restrict__ eps, int n_occ, int n_virt,
 }
 
 // Scales of the Pi contraction: sf[0] = x scale, sf[1] = B scale,
-// cfac[f] = multiplier of the weight table, pi_unscale[f] = 1 / (x scale * y scale).
+// ys[f] = scale of the prescaled operand X diag(c_f), pi_unscale[f] = 1 / (x scale * ys[f]).
 __global__ void k_scales_pi(const uint32_t* __restrict__ amax, int n_f, double* __restrict__ sf) {
     const double xmax = __uint_as_float(amax[0]);
     const double xs = pow2_for(xmax);
@@ -94,17 +94,52 @@ __global__ void k_scales_pi(const uint32_t* __restrict__ amax, int n_f, double* 
     }
     for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < n_f; f += gridDim.x * blockDim.x) {
         double ys = pow2_for((double)__uint_as_float(amax[2 + f]) * xmax);
-        sf[2 + f] = ys / xs;                   // cfac
-        sf[2 + n_f + f] = 1.0 / (xs * ys);     // pi_unscale
+        sf[2 + f] = ys;
+        sf[2 + n_f + f] = 1.0 / (xs * ys);
     }
 }
 
-__global__ void k_scale_weights(float* __restrict__ cw32, int64_t kpad, const double* __restrict__ cfac) {
-    const int f = blockIdx.y;
-    const float c = (float)cfac[f];
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < kpad;
-         k += (int64_t)gridDim.x * blockDim.x)
-        cw32[(int64_t)f * kpad + k] *= c;
+// Y_f = split(X diag(c_f) * ys[f]) for the weight vectors f0 .. f0+nfb-1 as
+// hi/lo panel planes [fb][npad][kpad] (layout of panel_off), from the FP32
+// row-major copy of X (zero padded).  One lane per row and 32-element k span:
+// it reads one 128-byte line of X and of c_f and writes four 16-byte words per
+// plane; the 64 lanes of a wave write 1 KiB runs.
+template <int ET>
+__global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad, const float* __restrict__ cw32,
+                           const double* __restrict__ ys, int f0, uint16_t* __restrict__ yh,
+                           uint16_t* __restrict__ yl) {
+    const int fb = blockIdx.y, f = f0 + fb;
+    const int lane = threadIdx.x & 63;
+    const int64_t ks = kpad / 32, kw = kpad / 8;
+    const int64_t nspan = (int64_t)(npad / 64) * ks;
+    const float s = (float)ys[f];
+    const float* cw = cw32 + (int64_t)f * kpad;
+    uint4* oh = reinterpret_cast<uint4*>(yh + (int64_t)fb * npad * kpad);
+    uint4* ol = reinterpret_cast<uint4*>(yl + (int64_t)fb * npad * kpad);
+    const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < nspan; w += wstride) {
+        const int64_t rb = w / ks, sp = w % ks;
+        const float4* xr = reinterpret_cast<const float4*>(x32 + (rb * 64 + lane) * kpad + sp * 32);
+        const float4* cr = reinterpret_cast<const float4*>(cw + sp * 32);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 x0 = xr[2 * g], x1 = xr[2 * g + 1], c0 = cr[2 * g], c1 = cr[2 * g + 1];
+            const float y[8] = {x0.x * c0.x * s, x0.y * c0.y * s, x0.z * c0.z * s, x0.w * c0.w * s,
+                                x1.x * c1.x * s, x1.y * c1.y * s, x1.z * c1.z * s, x1.w * c1.w * s};
+            uint32_t h[4], l[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint16_t h0 = Elem<ET>::bits(y[2 * e]), h1 = Elem<ET>::bits(y[2 * e + 1]);
+                const uint16_t l0 = Elem<ET>::bits(y[2 * e] - Elem<ET>::val(h0));
+                const uint16_t l1 = Elem<ET>::bits(y[2 * e + 1] - Elem<ET>::val(h1));
+                h[e] = h0 | ((uint32_t)h1 << 16);
+                l[e] = l0 | ((uint32_t)l1 << 16);
+            }
+            const int64_t word = (rb * kw + sp * 4 + g) * 64 + lane;
+            oh[word] = make_uint4(h[0], h[1], h[2], h[3]);
+            ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
+        }
+    }
 }
 
 // Scales of the W contraction: lam_scale[f], w_unscale[f] = 1 / (lam_scale * B scale).
@@ -126,25 +161,60 @@ __device__ inline void split_store(double v, uint16_t* hi, uint16_t* lo, int64_t
     lo[o] = Elem<ET>::bits((float)(v - (double)Elem<ET>::val(h)));
 }
 
-// src [rows][cols] (leading dim lds) -> hi, lo planes of src * scale [rpad][cpad]
-// (zero padded) and/or an FP64 padded copy.
-template <int ET>
-__global__ void k_split_pad(const double* __restrict__ src, int64_t lds, int rows, int64_t cols,
-                            const double* __restrict__ scale, uint16_t* __restrict__ hi,
-                            uint16_t* __restrict__ lo, double* __restrict__ f64, int rpad, int64_t cpad) {
+// src [rows][cols] (leading dim lds) -> FP64 copy [rpad][cpad], zero padded.
+__global__ void k_pad_f64(const double* __restrict__ src, int64_t lds, int rows, int64_t cols,
+                          double* __restrict__ f64, int64_t cpad) {
     const int r = blockIdx.y;
-    const double s = scale ? *scale : 1.0;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cpad;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        double v = (r < rows && c < cols) ? src[(int64_t)r * lds + c] : 0.0;
-        int64_t o = (int64_t)r * cpad + c;
-        if (hi) split_store<ET>(v * s, hi, lo, o);
-        if (f64) f64[o] = v;
+         c += (int64_t)gridDim.x * blockDim.x)
+        f64[(int64_t)r * cpad + c] = (r < rows && c < cols) ? src[(int64_t)r * lds + c] : 0.0;
+}
+
+// Plane z = blockIdx.y of src (+ z * sstride; [rows][cols], leading dim lds)
+// times scale[z] -> hi/lo panel planes (+ z * rpad * cpad) [rpad][cpad], zero
+// padded, and for plane 0 optionally an unscaled FP32 row-major copy.  One
+// lane per row and 8-element k-group (one 16-byte word per plane).
+template <int ET>
+__global__ void k_split_panel(const double* __restrict__ src, int64_t sstride, int64_t lds, int rows,
+                              int64_t cols, const double* __restrict__ scale, uint16_t* __restrict__ hi,
+                              uint16_t* __restrict__ lo, float* __restrict__ f32, int rpad, int64_t cpad) {
+    const int z = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t kw = cpad / 8, nw = (int64_t)(rpad / 64) * kw;
+    const double s = scale ? scale[z] : 1.0;
+    const double* sp = src + z * sstride;
+    uint4* oh = reinterpret_cast<uint4*>(hi + (int64_t)z * rpad * cpad);
+    uint4* ol = reinterpret_cast<uint4*>(lo + (int64_t)z * rpad * cpad);
+    const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < nw; w += wstride) {
+        const int64_t rb = w / kw, g = w % kw;
+        const int64_t p = rb * 64 + lane, k0 = g * 8;
+        double v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            v[e] = (p < rows && k0 + e < cols) ? sp[p * lds + k0 + e] : 0.0;
+        if (f32 && z == 0) {
+            float4* d = reinterpret_cast<float4*>(f32 + p * cpad + k0);
+            d[0] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+            d[1] = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+        }
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double a = v[2 * e] * s, b = v[2 * e + 1] * s;
+            const uint16_t ha = Elem<ET>::bits((float)a), hb = Elem<ET>::bits((float)b);
+            const uint16_t la = Elem<ET>::bits((float)(a - (double)Elem<ET>::val(ha)));
+            const uint16_t lb = Elem<ET>::bits((float)(b - (double)Elem<ET>::val(hb)));
+            h[e] = ha | ((uint32_t)hb << 16);
+            l[e] = la | ((uint32_t)lb << 16);
+        }
+        oh[w * 64 + lane] = make_uint4(h[0], h[1], h[2], h[3]);
+        ol[w * 64 + lane] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 }
 
-// o_nm [S][N][n_mo] -> B^T rows c = s*n_mo + m: f64 [cpad][npad] (+ hi/lo planes of
-// B * scale), LDS-tiled transpose, zero padded.  With rowsel, output row c takes
+// o_nm [S][N][n_mo] -> B^T rows c = s*n_mo + m: f64 [cpad][npad] (+ hi/lo panel
+// planes of B * scale), LDS-tiled transpose, zero padded.  With rowsel, output row c takes
 // source column rowsel[c].  Records max|B| into *bmax when given.
 template <int ET>
 __global__ void k_transpose_b(const double* __restrict__ onm, int S, int N, int n_mo,
@@ -178,9 +248,8 @@ __global__ void k_transpose_b(const double* __restrict__ onm, int S, int N, int 
         int c = c0 + yy, p = p0 + tx;
         if (c < cpad && p < npad) {
             double v = tile[tx][yy];
-            int64_t o = (int64_t)c * npad + p;
-            if (bt64) bt64[o] = v;
-            if (bh) split_store<ET>(v * s, bh, bl, o);
+            if (bt64) bt64[(int64_t)c * npad + p] = v;
+            if (bh) split_store<ET>(v * s, bh, bl, panel_off(c, p, npad));
         }
     }
 }
@@ -251,17 +320,6 @@ __global__ void k_finalize_lambda(double* __restrict__ E, int npad, const int* _
     }
 }
 
-// Full FP64 Lambda_f -> hi/lo planes of Lambda_f * lam_scale[f].
-template <int ET>
-__global__ void k_split_lambda(const double* __restrict__ lam, int64_t n2, const double* __restrict__ lam_scale,
-                               uint16_t* __restrict__ lh, uint16_t* __restrict__ ll) {
-    const int f = blockIdx.y;
-    const double s = lam_scale[f];
-    const double* src = lam + (int64_t)f * n2;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n2; t += (int64_t)gridDim.x * blockDim.x)
-        split_store<ET>(src[t] * s, lh + (int64_t)f * n2, ll + (int64_t)f * n2, t);
-}
-
 // W_im[s][m][f] = sum_I partial[f][I][s*n_mo + m]
 __global__ void k_reduce_w_im(const double* __restrict__ partial, int ni, int cpad, int n_im, int ncols,
                               double* __restrict__ w_im) {
@@ -323,21 +381,37 @@ void launch_scales_pi(hipStream_t s, const uint32_t* amax, int n_f, double* sf) 
     hipLaunchKernelGGL(k_scales_pi, dim3(1), dim3(256), 0, s, amax, n_f, sf);
 }
 
-void launch_scale_weights(hipStream_t s, float* cw32, int64_t kpad, int n_f, const double* cfac) {
-    hipLaunchKernelGGL(k_scale_weights, dim3(grid1(kpad, 4096), n_f), dim3(256), 0, s, cw32, kpad, cfac);
+void launch_prescale(hipStream_t s, int et, const float* x32, int npad, int64_t kpad, const float* cw32,
+                     const double* ys, int f0, int nfb, uint16_t* yh, uint16_t* yl) {
+    const int64_t waves = (int64_t)(npad / 64) * (kpad / 32);
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 4096)), nfb);
+    if (et == 1)
+        hipLaunchKernelGGL(k_prescale<1>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, yh, yl);
+    else
+        hipLaunchKernelGGL(k_prescale<0>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, yh, yl);
 }
 
 void launch_scales_w(hipStream_t s, const uint32_t* lmax, int n_f, double* sf, double* lam_scale, double* w_unscale) {
     hipLaunchKernelGGL(k_scales_w, dim3(1), dim3(256), 0, s, lmax, n_f, sf, lam_scale, w_unscale);
 }
 
-void launch_split_pad(hipStream_t s, int et, const double* src, int64_t lds, int rows, int64_t cols,
-                      const double* scale, uint16_t* hi, uint16_t* lo, double* f64, int rpad, int64_t cpad) {
+void launch_pad_f64(hipStream_t s, const double* src, int64_t lds, int rows, int64_t cols, double* f64, int rpad,
+                    int64_t cpad) {
     dim3 grid(grid1(cpad, 2048), rpad);
+    hipLaunchKernelGGL(k_pad_f64, grid, dim3(256), 0, s, src, lds, rows, cols, f64, cpad);
+}
+
+void launch_split_panel(hipStream_t s, int et, const double* src, int64_t sstride, int nz, int64_t lds, int rows,
+                        int64_t cols, const double* scale, uint16_t* hi, uint16_t* lo, float* f32, int rpad,
+                        int64_t cpad) {
+    const int64_t waves = (int64_t)(rpad / 64) * (cpad / 8);
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 4096)), nz);
     if (et == 1)
-        hipLaunchKernelGGL(k_split_pad<1>, grid, dim3(256), 0, s, src, lds, rows, cols, scale, hi, lo, f64, rpad, cpad);
+        hipLaunchKernelGGL(k_split_panel<1>, grid, dim3(256), 0, s, src, sstride, lds, rows, cols, scale, hi, lo,
+                           f32, rpad, cpad);
     else
-        hipLaunchKernelGGL(k_split_pad<0>, grid, dim3(256), 0, s, src, lds, rows, cols, scale, hi, lo, f64, rpad, cpad);
+        hipLaunchKernelGGL(k_split_panel<0>, grid, dim3(256), 0, s, src, sstride, lds, rows, cols, scale, hi, lo,
+                           f32, rpad, cpad);
 }
 
 void launch_transpose_b(hipStream_t s, int et, const double* onm, int S, int N, int n_mo, const int* rowsel,
@@ -359,16 +433,6 @@ void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, i
 void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax) {
     int nt = npad / 32, T = nt * (nt + 1) / 2;
     hipLaunchKernelGGL(k_finalize_lambda, dim3(T * n_f), dim3(256), 0, s, E, npad, idflag, lmax);
-}
-
-void launch_split_lambda(hipStream_t s, int et, const double* lam, int npad, int n_f, const double* lam_scale,
-                         uint16_t* lh, uint16_t* ll) {
-    int64_t n2 = (int64_t)npad * npad;
-    dim3 grid(grid1(n2, 4096), n_f);
-    if (et == 1)
-        hipLaunchKernelGGL(k_split_lambda<1>, grid, dim3(256), 0, s, lam, n2, lam_scale, lh, ll);
-    else
-        hipLaunchKernelGGL(k_split_lambda<0>, grid, dim3(256), 0, s, lam, n2, lam_scale, lh, ll);
 }
 
 void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out) {

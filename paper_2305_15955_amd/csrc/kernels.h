@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace cdwac {
 
 constexpr int CDWAC_FLAG_NOROOT_DEV = 1;
@@ -52,29 +54,37 @@ void launch_weights(hipStream_t s, const double* eps, int n_occ, int n_virt, dou
                     const double* zi, const int* part, int n_f, int64_t kpad, double* cw64, float* cw32,
                     uint32_t* cmax);
 void launch_scales_pi(hipStream_t s, const uint32_t* amax, int n_f, double* sf);
-void launch_scale_weights(hipStream_t s, float* cw32, int64_t kpad, int n_f, const double* cfac);
+void launch_prescale(hipStream_t s, int et, const float* x32, int npad, int64_t kpad, const float* cw32,
+                     const double* ys, int f0, int nfb, uint16_t* yh, uint16_t* yl);
 void launch_scales_w(hipStream_t s, const uint32_t* lmax, int n_f, double* sf, double* lam_scale, double* w_unscale);
-void launch_split_pad(hipStream_t s, int et, const double* src, int64_t lds, int rows, int64_t cols,
-                      const double* scale, uint16_t* hi, uint16_t* lo, double* f64, int rpad, int64_t cpad);
+void launch_pad_f64(hipStream_t s, const double* src, int64_t lds, int rows, int64_t cols, double* f64, int rpad,
+                    int64_t cpad);
+// nz planes src + z * sstride, scaled by scale[z], to hi/lo panel planes (panel_off)
+void launch_split_panel(hipStream_t s, int et, const double* src, int64_t sstride, int nz, int64_t lds, int rows,
+                        int64_t cols, const double* scale, uint16_t* hi, uint16_t* lo, float* f32, int rpad,
+                        int64_t cpad);
 void launch_transpose_b(hipStream_t s, int et, const double* onm, int S, int N, int n_mo, const int* rowsel,
                         int nrows, const double* scale, double* bt64, uint16_t* bh, uint16_t* bl, int cpad,
                         int npad, uint32_t* bmax, int* err);
 void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, int n_occ, double* sx);
 void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax);
-void launch_split_lambda(hipStream_t s, int et, const double* lam, int npad, int n_f, const double* lam_scale,
-                         uint16_t* lh, uint16_t* ll);
 void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out);
 void launch_reduce_w(hipStream_t s, const double* partial_im, const double* partial_re, int ni, int cpad,
                      int cfpad, int n_im, int n_re, int ncols, int nfit, double* w_im, double* w_re);
 
 // k_dense.hip
-void launch_pi(hipStream_t s, int prec, int npad, int64_t kpad, int n_f, const double* x64, const uint16_t* xh,
-               const uint16_t* xl, const double* cw64, const float* cw32, const double* pi_unscale,
-               const int* idflag, double* E);
+constexpr int kGemmRows = 256;   // row block of the 16-bit contraction (A operand)
+std::vector<int2> pi_tiles(int npad);
+std::vector<int2> w_tiles(int npad, int cpad);
+void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double* x64, const double* cw64,
+                   const int* idflag, double* E);
+void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, int f0, int nfb, const uint16_t* xh,
+                    const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* tiles, int n_tiles,
+                    const double* pi_unscale, const int* idflag, double* E);
 int w_partial_blocks(int prec, int npad);
 void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* lam64, const uint16_t* lh,
               const uint16_t* ll, const double* bt64, const uint16_t* bh, const uint16_t* bl, int cpad,
-              const double* w_unscale, double* partial);
+              const int2* tiles, int n_tiles, const double* w_unscale, double* partial);
 
 // k_sweep.hip
 void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dinv_r,

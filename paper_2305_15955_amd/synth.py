@@ -12,7 +12,8 @@ Energies are in Hartree.  Recipe (one ``numpy.random.default_rng(seed)`` per
 system, fixed draw order):
 
 1. core energies: one core at exactly -290 eV, or ``n_core`` cores drawn
-   uniformly in [-292, -288] eV and sorted;
+   uniformly in [-290.5, -289.5] eV (a 1 eV band of chemical shifts) and
+   sorted;
 2. valence energies uniform in [-30, -5] eV, sorted;
 3. virtual energies uniform in [0.5, 50] eV, sorted;
 4. O^{ia}_P ~ N(0, sigma^2) for every occupied i and virtual a, laid out as
@@ -25,6 +26,13 @@ system, fixed draw order):
 Step 6 is a modelling choice for synthetic data: with uncorrelated
 coefficients of equal size the core state has no distinct quasiparticle peak,
 while the damped coupling gives a single root with Z close to 0.9.
+
+The 1 eV core band keeps every quasiparticle energy (about 3 eV below its
+Kohn-Sham level) clear of the other cores' Kohn-Sham levels.  At omega = eps_m
+of an occupied m the residue term switches W^c_nm off (Eq. ffact) while the
+quadrature of the integral term, which has no node at zero, cannot follow:
+Sigma jumps by ~|W^c_nm(0)| there, and a root that would sit inside the jump
+does not exist (a 4 eV band put one of 16 cores there).
 """
 from __future__ import annotations
 
@@ -83,7 +91,7 @@ def make_system(n_mo: int, n_occ: int, n_aux: int, n_core: int, sigma: float,
     if n_core == 1:
         core = np.array([single_core_ev])
     else:
-        core = np.sort(rng.uniform(-292.0, -288.0, n_core))
+        core = np.sort(rng.uniform(-290.5, -289.5, n_core))
     val = np.sort(rng.uniform(-30.0, -5.0, n_occ - n_core))
     virt = np.sort(rng.uniform(0.5, 50.0, n_virt))
     eps = np.concatenate([core, val, virt]) / HARTREE_EV

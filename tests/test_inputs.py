@@ -10,7 +10,7 @@ def test_generator_shapes_and_symmetry():
     assert s.eps.shape == (40,) and np.all(np.diff(s.eps) > 0)
     assert s.o_ia.shape == (30, 8 * 32) and s.o_nm.shape == (3, 30, 40)
     ev = s.eps * synth.HARTREE_EV
-    assert np.all((ev[:3] > -292) & (ev[:3] < -288))
+    assert np.all((ev[:3] > -290.5) & (ev[:3] < -289.5))
     assert np.all((ev[3:8] > -30) & (ev[3:8] < -5))
     assert np.all((ev[8:] > 0.5) & (ev[8:] < 50))
     # O^{nm} consistent with O^{ia} for the virtual block, symmetric core block
