@@ -167,7 +167,7 @@ def main():
     issued = float(n_f) * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
     res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                        "frac": achieved / peak, "traffic": None,
-                       "kernel": "k_pi_split" if args.prec != "p64" else "k_pi_f64",
+                       "kernel": "k_pi_gemm" if args.prec != "p64" else "k_pi_f64",
                        "algorithmic_flop_per_launch": flops, "launch_ms": pi_s * 1e3,
                        "mfma_issued_frac": issued / pi_s / PEAK[args.prec]}
     res["stages_ms"] = stages
