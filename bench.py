@@ -161,8 +161,8 @@ def main():
         nt = npad // 64
         tile_elems = nt * (nt + 1) // 2 * 64 * 64
     else:
-        npad = int(math.ceil(s.n_aux / 256.0) * 256)
-        tile_elems = sum(min(2 * i + 2, npad // 128) for i in range(npad // 256)) * 256 * 128
+        nb = int(math.ceil(s.n_aux / 256.0))
+        tile_elems = nb * (nb + 1) // 2 * 256 * 256        # lower-triangle 256 x 256 tiles
     kpad = int(math.ceil(k_dim / 32.0) * 32)
     issued = float(n_f) * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
     res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

@@ -59,8 +59,8 @@ typedef enum {
     CDWAC_F16X3 = 3      /* fp16 hi/lo split of power-of-two-scaled operands (22-bit
                             significands), 3 products; same matrix-core rate as bf16 */
 } cdwac_prec;
-/* Every 16-bit mode accumulates in FP32 and flushes the sums into FP64 every
- * 2048 terms of the contraction. */
+/* Every 16-bit mode accumulates in FP32 in the matrix cores over the whole
+ * contraction; the sums are converted to FP64 at the end. */
 
 /* Per-state outcome flags. */
 enum {

@@ -208,7 +208,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     P.kpad = round_up(P.K, 32);
     P.npad = (int)round_up(P.n_aux, kGemmRows);
     P.nblk = P.npad / kNb;
-    P.cpad = (int)round_up((int64_t)P.S * P.n_mo, kPad);
+    P.cpad = (int)round_up((int64_t)P.S * P.n_mo, kGemmCols);
     P.ni = w_partial_blocks(P.prec, P.npad);
     // fit list
     std::vector<int> m0(P.S), m1(P.S), off(P.S), fs, fm;
@@ -221,7 +221,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
         }
     }
     P.n_fit = (int)fs.size();
-    P.cfpad = (int)round_up(std::max(P.n_fit, 1), kPad);
+    P.cfpad = (int)round_up(std::max(P.n_fit, 1), kGemmCols);
     if (hs) {
         hs->m0 = m0;
         hs->m1 = m1;

@@ -9,8 +9,7 @@
 //
 // Arithmetic: FP64 MFMA (v_mfma_f64_16x16x4), or 16-bit MFMA
 // (v_mfma_f32_32x32x16_{bf16,f16}) on operands split as hi + lo with the
-// products hi*hi + hi*lo + lo*hi accumulated in FP32 and flushed into FP64
-// every kFlush k-values, so the FP32 rounding of long sums stays bounded.
+// products hi*hi + hi*lo + lo*hi accumulated in FP32.
 #include "common.h"
 #include "kernels.h"
 
@@ -178,74 +177,78 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 // ============================================================================
 // 16-bit split MFMA contraction (v_mfma_f32_32x32x16_{bf16,f16}).
 //
-// One workgroup of 8 waves computes a GM x GN = 256 x 128 tile of A B^T with
-// both operands stored as hi/lo planes in the panel layout of panel_off (K is
-// the leading dimension lda = ldb), so each wave-wide load of one 64-row block
-// at one k-group reads 1 KiB of consecutive memory.  Each wave
-// owns 64 x 64 (2 x 2 MFMA blocks).  K advances in chunks of 32 through a
-// 3-stage LDS ring filled by direct global-to-LDS loads (no register
-// staging): chunk i+2 is in flight while chunk i is multiplied.  LDS layout
-// per stage: [plane][k-group of 8][row] x 16 bytes, so every lane's fragment
-// read is one contiguous 16-byte word.  Products hi*hi + hi*lo + lo*hi are
-// accumulated in FP32 and flushed into FP64 every kFlushChunks chunks.
-// Tiles come from a host-built list ordered in 2-D blocks, so the workgroups
-// an XCD runs together share operand panels in its L2.
+// One workgroup of 8 waves computes a 256 x 256 tile of A B^T with both
+// operands stored as hi/lo planes in the panel layout of panel_off (K is the
+// leading dimension lda = ldb), so each wave-wide load of one 64-row block at
+// one k-group reads 1 KiB of consecutive memory and lands in LDS through the
+// direct global-to-LDS path.  The waves form a 4 x 2 grid; each owns a 64 x 128
+// sub-tile (2 x 4 matrix-core blocks, 128 FP32 accumulators per lane).  K
+// advances in chunks of 32 through a 2-stage LDS ring of 64 KiB per stage:
+// chunk i+1 is in flight while chunk i is multiplied.  LDS layout per stage:
+// [operand][plane][k-group of 8][row] x 16 bytes, so every fragment read is one
+// contiguous 16-byte word per lane and a half-wave reads 512 consecutive
+// bytes (no bank conflicts).  Products hi*hi + hi*lo + lo*hi accumulate in
+// FP32 in the matrix cores over the whole contraction and are converted to
+// FP64 at the end.  Tiles come from a host-built list ordered in 4 x 8 blocks,
+// and the workgroups an XCD runs together share operand panels in its L2.
 // ============================================================================
 
-constexpr int GM = 256, GN = 128, GK = 32, NST = 3, kFlushChunks = 64;
+constexpr int GT = 256, GK = 32, KGR = GK / 8, NST = 2;
 constexpr int kGemmThreads = 512;
-constexpr int A_STAGE = 2 * 4 * GM;   // uint4 slots of A per stage
-constexpr int B_STAGE = 2 * 4 * GN;
-constexpr int STAGE = A_STAGE + B_STAGE;
+constexpr int OP_STAGE = 2 * KGR * GT;          // uint4 slots of one operand per stage
+constexpr int STAGE = 2 * OP_STAGE;
+constexpr int kLoadsPerWave = 2 * 2 * KGR * 4 / 8;
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// Issues this wave's share (6 of 48 row-block loads) of chunk k0 into stage st.
+// s_waitcnt immediates (gfx9 encoding): vmcnt(n) and lgkmcnt(0), expcnt open.
+constexpr int wait_vm_lgkm0(int n) { return ((n >> 4) << 14) | (7 << 4) | (n & 15); }
+
+// Workgroup barrier without the memory fence of __syncthreads(), whose
+// release semantics would also wait for the global-to-LDS loads still in
+// flight for the next chunk.  Callers wait for what must be complete first.
+__device__ inline void stage_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// Issues this wave's share (8 of 64 row-block loads) of chunk k0 into stage st.
 __device__ inline void gemm_issue(uint4* lds, int st, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
-                                  int64_t lda, const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl,
-                                  int64_t ldb, int64_t k0, int w, int lane) {
+                                  const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl, int64_t K,
+                                  int64_t k0, int w, int lane) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const int u = w * 6 + q;
-        const uint16_t* g;
-        int slot;
-        if (u < 32) {   // A: plane u/16, k-group (u/4)%4, row block u%4
-            const int pl = u >> 4, kg = (u >> 2) & 3, rb = u & 3;
-            g = (pl ? al : ah) + (int64_t)rb * 64 * lda + (k0 + kg * 8) * 64 + lane * 8;
-            slot = (pl * 4 + kg) * GM + rb * 64;
-        } else {        // B: plane v/8, k-group (v/2)%4, row block v%2
-            const int v = u - 32;
-            const int pl = v >> 3, kg = (v >> 1) & 3, rb = v & 1;
-            g = (pl ? bl : bh) + (int64_t)rb * 64 * ldb + (k0 + kg * 8) * 64 + lane * 8;
-            slot = A_STAGE + (pl * 4 + kg) * GN + rb * 64;
-        }
+    for (int q = 0; q < kLoadsPerWave; ++q) {
+        const int u = w * kLoadsPerWave + q;          // 0 .. 63
+        const int op = u >> 5, v = u & 31;            // operand A or B
+        const int pl = v >> 4, kg = (v >> 2) & 3, rb = v & 3;
+        const uint16_t* base = op ? (pl ? bl : bh) : (pl ? al : ah);
+        const uint16_t* g = base + (int64_t)rb * 64 * K + (k0 + kg * 8) * 64 + lane * 8;
+        const int slot = op * OP_STAGE + (pl * KGR + kg) * GT + rb * 64;
         __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(lds + st * STAGE + slot), 16, 0, 0);
     }
 }
 
 template <int ET, bool SPLIT>
-__device__ inline void gemm_chunk(const uint4* lds, int st, int wr, int wc, int lane, v16f (&acc)[2][2]) {
+__device__ inline void gemm_chunk(const uint4* lds, int st, int r0, int c0, int lane, v16f (&acc)[2][4]) {
     typedef typename Elem<ET>::vec V;
     const uint4* sa = lds + st * STAGE;
-    const uint4* sb = sa + A_STAGE;
+    const uint4* sb = sa + OP_STAGE;
     const int r = lane & 31, hg = lane >> 5;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < GK / 16; ++ks) {
         const int kg = ks * 2 + hg;
-        V ahv[2], alv[2], bhv[2], blv[2];
+        V ahv[2], alv[2], bhv[4], blv[4];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            ahv[b] = __builtin_bit_cast(V, sa[kg * GM + wr * 64 + b * 32 + r]);
-            bhv[b] = __builtin_bit_cast(V, sb[kg * GN + wc * 64 + b * 32 + r]);
-            if (SPLIT) {
-                alv[b] = __builtin_bit_cast(V, sa[(4 + kg) * GM + wr * 64 + b * 32 + r]);
-                blv[b] = __builtin_bit_cast(V, sb[(4 + kg) * GN + wc * 64 + b * 32 + r]);
-            }
+            ahv[b] = __builtin_bit_cast(V, sa[kg * GT + r0 + b * 32 + r]);
+            if (SPLIT) alv[b] = __builtin_bit_cast(V, sa[(KGR + kg) * GT + r0 + b * 32 + r]);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            bhv[b] = __builtin_bit_cast(V, sb[kg * GT + c0 + b * 32 + r]);
+            if (SPLIT) blv[b] = __builtin_bit_cast(V, sb[(KGR + kg) * GT + c0 + b * 32 + r]);
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
+            for (int bj = 0; bj < 4; ++bj) {
                 acc[bi][bj] = Elem<ET>::mfma(ahv[bi], bhv[bj], acc[bi][bj]);
                 if (SPLIT) {
                     acc[bi][bj] = Elem<ET>::mfma(ahv[bi], blv[bj], acc[bi][bj]);
@@ -255,59 +258,36 @@ __device__ inline void gemm_chunk(const uint4* lds, int st, int wr, int wc, int 
     }
 }
 
-// s_waitcnt immediates (gfx9 encoding, other counters left open).
-constexpr int kWaitVm6 = (15 << 8) | (7 << 4) | 6;
-constexpr int kWaitVm0 = (15 << 8) | (7 << 4) | 0;
-
-// accd = A[rows a0..a0+GM) * B[rows b0..b0+GN)^T over K (multiple of GK).
+// acc = A[rows 0..256) * B[rows 0..256)^T over K (multiple of GK); A and B
+// point at the first row block of the tile.  Wave w owns rows
+// 64 (w / 2) .. +64 and columns 128 (w % 2) .. +128.
 template <int ET, bool SPLIT>
 __device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
-                                 int64_t lda, const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl,
-                                 int64_t ldb, int64_t K, double (&accd)[2][2][16]) {
+                                 const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl, int64_t K,
+                                 v16f (&acc)[2][4]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wr = w >> 1, wc = w & 1;
+    const int r0 = (w >> 1) * 64, c0 = (w & 1) * 128;
     const int64_t nk = K / GK;
-    // two-level FP32 sums: acc holds the current kFlushChunks chunks, tot the
-    // flushed ones, so each rounding is relative to a partial sum of at most
-    // 2048 terms or to the running total once per flush
-    v16f acc[2][2], tot[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            acc[bi][bj] = v16f{};
-            tot[bi][bj] = v16f{};
-        }
-    gemm_issue(lds, 0, ah, al, lda, bh, bl, ldb, 0, w, lane);
-    if (nk > 1) gemm_issue(lds, 1, ah, al, lda, bh, bl, ldb, GK, w, lane);
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v16f{};
+    gemm_issue(lds, 0, ah, al, bh, bl, K, 0, w, lane);
     for (int64_t i = 0; i < nk; ++i) {
-        if (i + 1 < nk) __builtin_amdgcn_s_waitcnt(kWaitVm6);
-        else __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        __syncthreads();
-        if (i + 2 < nk) gemm_issue(lds, (int)((i + 2) % NST), ah, al, lda, bh, bl, ldb, (i + 2) * GK, w, lane);
-        gemm_chunk<ET, SPLIT>(lds, (int)(i % NST), wr, wc, lane, acc);
-        if ((i + 1) % kFlushChunks == 0 || i + 1 == nk) {
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    tot[bi][bj] += acc[bi][bj];
-                    acc[bi][bj] = v16f{};
-                }
-        }
+        // chunk i has landed (own loads) and every wave is done with chunk i-1
+        __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+        stage_barrier();
+        if (i + 1 < nk) gemm_issue(lds, (int)((i + 1) % NST), ah, al, bh, bl, K, (i + 1) * GK, w, lane);
+        gemm_chunk<ET, SPLIT>(lds, (int)(i % NST), r0, c0, lane, acc);
     }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) accd[bi][bj][v] = (double)tot[bi][bj][v];
 }
 
-// Row of the output element held by (lane, v) inside a wave's 64 x 64 block bi.
-__device__ inline int out_row(int wr, int bi, int lane, int v) {
-    return wr * 64 + bi * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+// Row and column inside the tile of the output element held by (lane, v) of
+// block (bi, bj) of wave w.
+__device__ inline int out_row(int w, int bi, int lane, int v) {
+    return (w >> 1) * 64 + bi * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
 }
+__device__ inline int out_col(int w, int bj, int lane) { return (w & 1) * 128 + bj * 32 + (lane & 31); }
 
 // eps_f = delta_f I - Pi_f for the listed tiles of batch f (B = prescaled Y_f).
 template <int ET, bool SPLIT>
@@ -324,23 +304,23 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
     const int fb = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
     const int I = tile.x, J = tile.y, f = f0 + fb;
-    double accd[2][2][16];
-    const int64_t ao = (int64_t)I * GM * kpad;
-    const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GN * kpad;
-    gemm_tile<ET, SPLIT>(lds, xh + ao, xl + ao, kpad, yh + bo, yl + bo, kpad, kpad, accd);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+    const int64_t ao = (int64_t)I * GT * kpad;
+    const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GT * kpad;
+    v16f acc[2][4];
+    gemm_tile<ET, SPLIT>(lds, xh + ao, xl + ao, yh + bo, yl + bo, kpad, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double id = idflag[f] ? 1.0 : 0.0;
     const double us = pi_unscale[f];
     double* Ef = E + (int64_t)f * npad * npad;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                int P = I * GM + out_row(wr, bi, lane, v);
-                int Q = J * GN + wc * 64 + bj * 32 + (lane & 31);
-                Ef[(int64_t)P * npad + Q] = (P == Q ? id : 0.0) - accd[bi][bj][v] * us;
+                const int P = I * GT + out_row(w, bi, lane, v);
+                const int Q = J * GT + out_col(w, bj, lane);
+                Ef[(int64_t)P * npad + Q] = (P == Q ? id : 0.0) - (double)acc[bi][bj][v] * us;
             }
 }
 
@@ -355,34 +335,34 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
                                                          const double* __restrict__ w_unscale,
                                                          double* __restrict__ partial) {
     __shared__ uint4 lds[NST * STAGE];
-    __shared__ double red[4][GN];
+    __shared__ double red[4][GT];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fl = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
     const int I = tile.x, J = tile.y;
-    const int ni = npad / GM;
-    const int64_t lo = (int64_t)(f0 + fl) * npad * npad + (int64_t)I * GM * npad;
-    const int64_t bo = (int64_t)J * GN * npad;
-    double accd[2][2][16];
-    gemm_tile<ET, SPLIT>(lds, lh + lo, ll + lo, npad, bh + bo, bl + bo, npad, npad, accd);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+    const int ni = npad / GT;
+    const int64_t lo = (int64_t)(f0 + fl) * npad * npad + (int64_t)I * GT * npad;
+    const int64_t bo = (int64_t)J * GT * npad;
+    v16f acc[2][4];
+    gemm_tile<ET, SPLIT>(lds, lh + lo, ll + lo, bh + bo, bl + bo, npad, acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double us = w_unscale[f0 + fl];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int c = J * GN + wc * 64 + bj * 32 + (lane & 31);
-        const double* brow = bt64 + (int64_t)c * npad + I * GM;
+    for (int bj = 0; bj < 4; ++bj) {
+        const int c = J * GT + out_col(w, bj, lane);
+        const double* brow = bt64 + (int64_t)c * npad + I * GT;
         double s = 0.0;
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) s += brow[out_row(wr, bi, lane, v)] * accd[bi][bj][v];
+            for (int v = 0; v < 16; ++v) s += brow[out_row(w, bi, lane, v)] * (double)acc[bi][bj][v];
         s *= us;
         s += __shfl_xor(s, 32);
-        if (lane < 32) red[wr][wc * 64 + bj * 32 + lane] = s;
+        if (lane < 32) red[w >> 1][out_col(w, bj, lane)] = s;
     }
     __syncthreads();
-    if (threadIdx.x < GN) {
-        int c = J * GN + threadIdx.x;
+    if (threadIdx.x < GT) {
+        const int c = J * GT + threadIdx.x;
         partial[((int64_t)fl * ni + I) * cpad + c] =
             red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
     }
@@ -392,24 +372,24 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
 // Host side: tile lists and launchers
 // ============================================================================
 
-// Tiles (I, J) of GM x GN covering the lower triangle of an npad x npad
-// matrix (J <= 2I + 1), in 4 x 8 blocks so that consecutive tiles share
-// operand panels.
+// Tiles (I, J), J <= I, of 256 x 256 covering the lower triangle of an
+// npad x npad matrix, in 4 x 8 blocks so that consecutive tiles share operand
+// panels.
 std::vector<int2> pi_tiles(int npad) {
     std::vector<int2> out;
-    const int nI = npad / GM, nJ = npad / GN;
-    for (int I0 = 0; I0 < nI; I0 += 4)
-        for (int J0 = 0; J0 < nJ; J0 += 8)
-            for (int I = I0; I < std::min(nI, I0 + 4); ++I)
-                for (int J = J0; J < std::min(nJ, J0 + 8); ++J)
-                    if (J <= 2 * I + 1) out.push_back(make_int2(I, J));
+    const int n = npad / GT;
+    for (int I0 = 0; I0 < n; I0 += 4)
+        for (int J0 = 0; J0 < n; J0 += 8)
+            for (int I = I0; I < std::min(n, I0 + 4); ++I)
+                for (int J = J0; J < std::min(n, J0 + 8); ++J)
+                    if (J <= I) out.push_back(make_int2(I, J));
     return out;
 }
 
 // Full ni x nc grid of W tiles in 4 x 8 blocks.
 std::vector<int2> w_tiles(int npad, int cpad) {
     std::vector<int2> out;
-    const int nI = npad / GM, nJ = cpad / GN;
+    const int nI = npad / GT, nJ = cpad / GT;
     for (int I0 = 0; I0 < nI; I0 += 4)
         for (int J0 = 0; J0 < nJ; J0 += 8)
             for (int I = I0; I < std::min(nI, I0 + 4); ++I)
@@ -438,7 +418,7 @@ void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, int f0, int
                            idflag, E, npad);
 }
 
-int w_partial_blocks(int prec, int npad) { return npad / (prec == PREC_P64 ? F_BT : GM); }
+int w_partial_blocks(int prec, int npad) { return npad / (prec == PREC_P64 ? F_BT : GT); }
 
 void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* lam64, const uint16_t* lh,
               const uint16_t* ll, const double* bt64, const uint16_t* bh, const uint16_t* bl, int cpad,

@@ -74,6 +74,7 @@ void launch_reduce_w(hipStream_t s, const double* partial_im, const double* part
 
 // k_dense.hip
 constexpr int kGemmRows = 256;   // row block of the 16-bit contraction (A operand)
+constexpr int kGemmCols = 256;   // column block (B operand rows)
 std::vector<int2> pi_tiles(int npad);
 std::vector<int2> w_tiles(int npad, int cpad);
 void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double* x64, const double* cw64,

@@ -96,12 +96,16 @@ def test_naux5000_sampled_pi_and_properties(lib):
     pairs = [(int(p), int(q)) for p, q in zip(rng.integers(0, s.n_aux, 12), rng.integers(0, s.n_aux, 12))]
     pairs += [(0, 0), (s.n_aux - 1, s.n_aux - 1), (s.n_aux - 1, 0)]
     zs = [1j * case.freq[5], case.ref_re[4] + 1e-3j]
-    for prec, tol in (("p64", 1e-12), ("f16x3", 2e-6)):
+    # fp16 split: products exact to ~2^-22, but FP32 accumulation over
+    # K / 16 = 19 532 matrix-core steps gives ~sqrt(19 532) * 2^-24 = 8e-6
+    # relative to the largest partial sums
+    for prec, tol in (("p64", 1e-12), ("f16x3", 3e-5)):
         pis = lib.cdwac_polarizability(sysc, zs, prec=prec)
         for j, z in enumerate(zs):
             ref = R.polarizability_entries(s.o_ia, s.eps, s.n_occ, z, s.spin, pairs)
             got = np.array([pis[j][p, q] for p, q in pairs])
             scale = np.max(np.abs(np.diagonal(pis[j])))
+            print(prec, j, "max |dPi| / max|diag|", np.max(np.abs(got - ref)) / scale)
             assert np.max(np.abs(got - ref)) <= tol * scale, (prec, j)
         del pis
     qp = {}
