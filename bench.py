@@ -136,9 +136,10 @@ def main():
             log(f"step {prec} {i + 1}/{steps} done")
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / max(steps, 1)
-        return out, dt, {k: v / max(steps, 1) for k, v in stage_sum.items()}
+        launches = lib.cdwac_get_timing_segments()
+        return out, dt, {k: v / max(steps, 1) for k, v in stage_sum.items()}, launches
 
-    out, dt, stages = run_steps(args.prec, use_mlp, args.warmup, args.steps)
+    out, dt, stages, launches = run_steps(args.prec, use_mlp, args.warmup, args.steps)
     qps = s.n_states / dt
     res = {"metric": "core QP energies/sec at N_aux=5000 (mixed+MLP vs FP64), meV err, MFMA util",
            "value": qps, "unit": "core QP energies/s", "n_gpus": 1, "steps": args.steps,
@@ -149,33 +150,36 @@ def main():
                       "n_states": s.n_states, "n_freq": len(freq), "n_pade": len(ref_im) + len(ref_re),
                       "contraction_precision": args.prec, "mlp_seed": use_mlp}}
 
-    # roofline of the dominant kernel (polarizability, one launch per step)
+    # roofline of the dominant kernel: the polarizability contraction, one
+    # launch per batch of frequency planes; achieved = algorithmic flops of
+    # one launch / its average duration (HIP events on the library's stream)
     n_f = len(freq) + 2 * len(ref_re)
     k_dim = s.o_ia.shape[1]
-    flops = float(n_f) * s.n_aux * (s.n_aux + 1) * k_dim        # lower-triangle SYRK, 2 flop/MAC
-    pi_s = stages["polarizability"] * 1e-3
-    achieved = flops / pi_s / 1e12
+    n_launch = max(int(launches["polarizability"]), 1)
+    flops = float(n_f) * s.n_aux * (s.n_aux + 1) * k_dim / n_launch   # lower-triangle SYRK, 2 flop/MAC
+    launch_s = stages["polarizability"] * 1e-3 / n_launch
+    achieved = flops / launch_s / 1e12
     peak = PEAK[args.prec] / 1e12
+    nb = int(math.ceil(s.n_aux / 256.0))
+    kpad = int(math.ceil(k_dim / 32.0) * 32)
     if args.prec == "p64":
-        npad = int(math.ceil(s.n_aux / 256.0) * 256)
-        nt = npad // 64
+        nt = nb * 4
         tile_elems = nt * (nt + 1) // 2 * 64 * 64
     else:
-        nb = int(math.ceil(s.n_aux / 256.0))
         tile_elems = nb * (nb + 1) // 2 * 256 * 256        # lower-triangle 256 x 256 tiles
-    kpad = int(math.ceil(k_dim / 32.0) * 32)
-    issued = float(n_f) * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
+    issued = float(n_f) / n_launch * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
     res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                        "frac": achieved / peak, "traffic": None,
                        "kernel": "k_pi_gemm" if args.prec != "p64" else "k_pi_f64",
-                       "algorithmic_flop_per_launch": flops, "launch_ms": pi_s * 1e3,
-                       "mfma_issued_frac": issued / pi_s / PEAK[args.prec]}
+                       "launches": n_launch, "algorithmic_flop_per_launch": flops,
+                       "launch_ms": launch_s * 1e3,
+                       "mfma_issued_frac": issued / launch_s / PEAK[args.prec]}
     res["stages_ms"] = stages
     res["qp_ev"] = [o["qp"] * synth.HARTREE_EV for o in out]
     res["n_evals_mean"] = float(np.mean([o["n_evals"] for o in out]))
 
     if args.fp64_steps > 0 and args.prec != "p64":
-        out64, dt64, st64 = run_steps("p64", False, 0, args.fp64_steps)
+        out64, dt64, st64, _ = run_steps("p64", False, 0, args.fp64_steps)
         err = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(out, out64)]
         res["fp64_path"] = {"value": s.n_states / dt64, "ms_per_step": dt64 * 1e3, "stages_ms": st64,
                             "n_evals_mean": float(np.mean([o["n_evals"] for o in out64]))}

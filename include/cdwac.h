@@ -188,6 +188,11 @@ int cdwac_set_timing(cdwac_ctx *ctx, int on);
 #define CDWAC_N_STAGES 8
 int cdwac_get_timing(const cdwac_ctx *ctx, double *ms, int32_t n);
 
+/* Number of timed segments behind each stage of cdwac_get_timing (same
+ * order).  Stage 1 times each polarizability launch as one segment, so
+ * ms[1] / count[1] is the average duration of one contraction launch. */
+int cdwac_get_timing_segments(const cdwac_ctx *ctx, int32_t *count, int32_t n);
+
 /* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------
  * Parameter vector (CDWAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64],
  * b2[64], W3[1][64], b3[1].  Features of a state (Ha): eps_n, eps_F,

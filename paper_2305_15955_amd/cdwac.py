@@ -82,6 +82,7 @@ _SIGNATURES = {
                                            ctypes.c_int32, _vp, _vp, _vp]),
     "cdwac_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cdwac_get_timing": (ctypes.c_int, [_vp, _f64p, ctypes.c_int32]),
+    "cdwac_get_timing_segments": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "cdwac_mlp_set_model": (ctypes.c_int, [_vp, _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_float]),
     "cdwac_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "cdwac_mlp_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
@@ -325,6 +326,11 @@ class Cdwac:
         ms = np.zeros(len(self.STAGES))
         _check(self.ctx, self.lib.cdwac_get_timing(self.ctx, _np_ptr(ms, ctypes.c_double), len(ms)))
         return dict(zip(self.STAGES, ms.tolist()))
+
+    def cdwac_get_timing_segments(self):
+        n = np.zeros(len(self.STAGES), np.int32)
+        _check(self.ctx, self.lib.cdwac_get_timing_segments(self.ctx, _np_ptr(n, ctypes.c_int32), len(n)))
+        return dict(zip(self.STAGES, n.tolist()))
 
     # -- learned seed -------------------------------------------------------
     def cdwac_mlp_set_model(self, theta, mu, sd, out_mu: float, out_sd: float):

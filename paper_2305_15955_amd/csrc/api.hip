@@ -93,6 +93,7 @@ struct cdwac_ctx {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     double stage_ms[CDWAC_N_STAGES] = {};
+    int32_t stage_n[CDWAC_N_STAGES] = {};
 };
 
 namespace {
@@ -389,6 +390,7 @@ int seg_collect(cdwac_ctx* ctx) {
         float ms = 0.f;
         HIPCK(hipEventElapsedTime(&ms, g.a, g.b));
         ctx->stage_ms[g.stage] += ms;
+        ctx->stage_n[g.stage] += 1;
     }
     ctx->segs.clear();
     ctx->pool_used = 0;
@@ -552,6 +554,7 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     int* err = at<int>(ctx, P.err);
     HIPCK(hipMemsetAsync(err, 0, sizeof(int) * 4, st));
     for (double& x : ctx->stage_ms) x = 0.0;
+    for (int32_t& x : ctx->stage_n) x = 0;
     ctx->segs.clear();
     ctx->pool_used = 0;
 
@@ -697,6 +700,7 @@ int cdwac_qp(cdwac_ctx* ctx, const double* vxc, cdwac_state_out* out) {
     if (vxc) TRY(upload(ctx, at<double>(ctx, P.vxc), vxc, P.S));
     QpArgs a = qp_args(ctx);
     ctx->stage_ms[6] = 0.0;
+    ctx->stage_n[6] = 0;
     TRY(seg_begin(ctx, 6));
     launch_qp(st, a, at<QpOut>(ctx, P.qpout));
     LAUNCHCK();
@@ -903,6 +907,12 @@ int cdwac_set_timing(cdwac_ctx* ctx, int on) {
 int cdwac_get_timing(const cdwac_ctx* ctx, double* ms, int32_t n) {
     if (!ctx || !ms || n < 0) return CDWAC_EINVAL;
     for (int i = 0; i < n && i < CDWAC_N_STAGES; ++i) ms[i] = ctx->stage_ms[i];
+    return CDWAC_OK;
+}
+
+int cdwac_get_timing_segments(const cdwac_ctx* ctx, int32_t* count, int32_t n) {
+    if (!ctx || !count || n < 0) return CDWAC_EINVAL;
+    for (int i = 0; i < n && i < CDWAC_N_STAGES; ++i) count[i] = ctx->stage_n[i];
     return CDWAC_OK;
 }
 

@@ -102,42 +102,48 @@ __global__ void k_scales_pi(const uint32_t* __restrict__ amax, int n_f, double* 
 // Y_f = split(X diag(c_f) * ys[f]) for the weight vectors f0 .. f0+nfb-1 as
 // hi/lo panel planes [fb][npad][kpad] (layout of panel_off), from the FP32
 // row-major copy of X (zero padded).  One lane per row and 32-element k span:
-// it reads one 128-byte line of X and of c_f and writes four 16-byte words per
-// plane; the 64 lanes of a wave write 1 KiB runs.
+// it reads one 128-byte line of X once and, for every plane of the batch, the
+// matching line of c_f and four 16-byte words per output plane; the 64 lanes
+// of a wave write 1 KiB runs.
 template <int ET>
 __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad, const float* __restrict__ cw32,
-                           const double* __restrict__ ys, int f0, uint16_t* __restrict__ yh,
+                           const double* __restrict__ ys, int f0, int nfb, uint16_t* __restrict__ yh,
                            uint16_t* __restrict__ yl) {
-    const int fb = blockIdx.y, f = f0 + fb;
     const int lane = threadIdx.x & 63;
     const int64_t ks = kpad / 32, kw = kpad / 8;
     const int64_t nspan = (int64_t)(npad / 64) * ks;
-    const float s = (float)ys[f];
-    const float* cw = cw32 + (int64_t)f * kpad;
-    uint4* oh = reinterpret_cast<uint4*>(yh + (int64_t)fb * npad * kpad);
-    uint4* ol = reinterpret_cast<uint4*>(yl + (int64_t)fb * npad * kpad);
+    const int64_t plane = (int64_t)npad * kpad;
     const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < nspan; w += wstride) {
         const int64_t rb = w / ks, sp = w % ks;
         const float4* xr = reinterpret_cast<const float4*>(x32 + (rb * 64 + lane) * kpad + sp * 32);
-        const float4* cr = reinterpret_cast<const float4*>(cw + sp * 32);
+        float4 x[8];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const float4 x0 = xr[2 * g], x1 = xr[2 * g + 1], c0 = cr[2 * g], c1 = cr[2 * g + 1];
-            const float y[8] = {x0.x * c0.x * s, x0.y * c0.y * s, x0.z * c0.z * s, x0.w * c0.w * s,
-                                x1.x * c1.x * s, x1.y * c1.y * s, x1.z * c1.z * s, x1.w * c1.w * s};
-            uint32_t h[4], l[4];
+        for (int q = 0; q < 8; ++q) x[q] = xr[q];
+        for (int fb = 0; fb < nfb; ++fb) {
+            const int f = f0 + fb;
+            const float s = (float)ys[f];
+            const float4* cr = reinterpret_cast<const float4*>(cw32 + (int64_t)f * kpad + sp * 32);
+            uint4* oh = reinterpret_cast<uint4*>(yh + fb * plane);
+            uint4* ol = reinterpret_cast<uint4*>(yl + fb * plane);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint16_t h0 = Elem<ET>::bits(y[2 * e]), h1 = Elem<ET>::bits(y[2 * e + 1]);
-                const uint16_t l0 = Elem<ET>::bits(y[2 * e] - Elem<ET>::val(h0));
-                const uint16_t l1 = Elem<ET>::bits(y[2 * e + 1] - Elem<ET>::val(h1));
-                h[e] = h0 | ((uint32_t)h1 << 16);
-                l[e] = l0 | ((uint32_t)l1 << 16);
+            for (int g = 0; g < 4; ++g) {
+                const float4 x0 = x[2 * g], x1 = x[2 * g + 1], c0 = cr[2 * g], c1 = cr[2 * g + 1];
+                const float y[8] = {x0.x * c0.x * s, x0.y * c0.y * s, x0.z * c0.z * s, x0.w * c0.w * s,
+                                    x1.x * c1.x * s, x1.y * c1.y * s, x1.z * c1.z * s, x1.w * c1.w * s};
+                uint32_t h[4], l[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint16_t h0 = Elem<ET>::bits(y[2 * e]), h1 = Elem<ET>::bits(y[2 * e + 1]);
+                    const uint16_t l0 = Elem<ET>::bits(y[2 * e] - Elem<ET>::val(h0));
+                    const uint16_t l1 = Elem<ET>::bits(y[2 * e + 1] - Elem<ET>::val(h1));
+                    h[e] = h0 | ((uint32_t)h1 << 16);
+                    l[e] = l0 | ((uint32_t)l1 << 16);
+                }
+                const int64_t word = (rb * kw + sp * 4 + g) * 64 + lane;
+                oh[word] = make_uint4(h[0], h[1], h[2], h[3]);
+                ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
             }
-            const int64_t word = (rb * kw + sp * 4 + g) * 64 + lane;
-            oh[word] = make_uint4(h[0], h[1], h[2], h[3]);
-            ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
         }
     }
 }
@@ -384,11 +390,11 @@ void launch_scales_pi(hipStream_t s, const uint32_t* amax, int n_f, double* sf) 
 void launch_prescale(hipStream_t s, int et, const float* x32, int npad, int64_t kpad, const float* cw32,
                      const double* ys, int f0, int nfb, uint16_t* yh, uint16_t* yl) {
     const int64_t waves = (int64_t)(npad / 64) * (kpad / 32);
-    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 4096)), nfb);
+    dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 8192)));
     if (et == 1)
-        hipLaunchKernelGGL(k_prescale<1>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, yh, yl);
+        hipLaunchKernelGGL(k_prescale<1>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, nfb, yh, yl);
     else
-        hipLaunchKernelGGL(k_prescale<0>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, yh, yl);
+        hipLaunchKernelGGL(k_prescale<0>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, nfb, yh, yl);
 }
 
 void launch_scales_w(hipStream_t s, const uint32_t* lmax, int n_f, double* sf, double* lam_scale, double* w_unscale) {
