@@ -37,6 +37,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(prec, workload):
+    """HBM bytes per k_pi_gemm launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy), or None if
+    the summary is for another kernel source or configuration."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_pi_gemm_{workload}_hbm_traffic.md")
+    if prec != "f16x3" or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "k_dense_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    src = os.path.join(ROOT, "paper_2305_15955_amd", "csrc", "k_dense.hip")
+    if vals.get("k_dense_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def build_inputs(name):
     from paper_2305_15955_amd import grids, synth
     spec = synth.WORKLOADS[name]
@@ -85,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="precision_naux5000")
     ap.add_argument("--prec", default="f16x3", choices=["f16x3", "b16x3", "b16", "p64"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 GPU path")
+    ap.add_argument("--rank-tol", type=float, default=1e-10,
+                    help="imaginary-node decomposition tolerance of the 16-bit path (0: every node)")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -115,7 +136,8 @@ def main():
 
     def params(prec, mlp):
         return lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec=prec,
-                               pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4 / synth.HARTREE_EV)
+                               pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4 / synth.HARTREE_EV,
+                               freq_rank_tol=args.rank_tol if prec != "p64" else 0.0)
 
     sysc, keep = lib.make_system(s, o_ia_dev=o_ia, o_nm_dev=o_nm)
     lib.cdwac_set_timing(True)
@@ -148,12 +170,19 @@ def main():
            "data": "synthetic (seeded Gaussian RI coefficients, no molecule)",
            "config": {"workload": args.workload, "n_aux": s.n_aux, "n_mo": s.n_mo, "n_occ": s.n_occ,
                       "n_states": s.n_states, "n_freq": len(freq), "n_pade": len(ref_im) + len(ref_re),
-                      "contraction_precision": args.prec, "mlp_seed": use_mlp}}
+                      "contraction_precision": args.prec, "mlp_seed": use_mlp,
+                      "freq_rank_tol": args.rank_tol if args.prec != "p64" else 0.0}}
 
     # roofline of the dominant kernel: the polarizability contraction, one
     # launch per batch of frequency planes; achieved = algorithmic flops of
     # one launch / its average duration (HIP events on the library's stream)
-    n_f = len(freq) + 2 * len(ref_re)
+    n_im_planes = len(freq)
+    if args.prec != "p64" and args.rank_tol > 0:
+        dmin = s.eps[s.n_occ] - s.eps[s.n_occ - 1]
+        dmax = s.eps[-1] - s.eps[0]
+        n_im_planes = len(cdwac.freq_decomposition(freq, dmin, dmax, args.rank_tol)[0])
+    n_f = n_im_planes + 2 * len(ref_re)          # planes the contraction computes
+    res["config"]["contracted_planes"] = n_f
     k_dim = s.o_ia.shape[1]
     n_launch = max(int(launches["polarizability"]), 1)
     flops = float(n_f) * s.n_aux * (s.n_aux + 1) * k_dim / n_launch   # lower-triangle SYRK, 2 flop/MAC
@@ -168,8 +197,9 @@ def main():
     else:
         tile_elems = nb * (nb + 1) // 2 * 256 * 256        # lower-triangle 256 x 256 tiles
     issued = float(n_f) / n_launch * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
+    traffic = measured_traffic(args.prec, args.workload) if args.rank_tol == 1e-10 else None
     res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                       "frac": achieved / peak, "traffic": None,
+                       "frac": achieved / peak, "traffic": traffic,
                        "kernel": "k_pi_gemm" if args.prec != "p64" else "k_pi_f64",
                        "launches": n_launch, "algorithmic_flop_per_launch": flops,
                        "launch_ms": launch_s * 1e3,

@@ -48,7 +48,8 @@ class CdwacParams(ctypes.Structure):
                 ("ref_re", _f64p), ("eta_ref", ctypes.c_double), ("eta", ctypes.c_double),
                 ("pade_tol", ctypes.c_double), ("win_lo", _f64p), ("win_hi", _f64p),
                 ("qp_tol", ctypes.c_double), ("qp_maxit", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("use_mlp_seed", ctypes.c_int32), ("mlp_accept", ctypes.c_double)]
+                ("use_mlp_seed", ctypes.c_int32), ("mlp_accept", ctypes.c_double),
+                ("freq_rank_tol", ctypes.c_double)]
 
 
 class CdwacStateOut(ctypes.Structure):
@@ -82,6 +83,10 @@ _SIGNATURES = {
                                            ctypes.c_int32, _vp, _vp, _vp]),
     "cdwac_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cdwac_get_timing": (ctypes.c_int, [_vp, _f64p, ctypes.c_int32]),
+    "cdwac_freq_decomposition": (ctypes.c_int, [ctypes.c_int32, _f64p, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                                 _f64p]),
     "cdwac_get_timing_segments": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "cdwac_mlp_set_model": (ctypes.c_int, [_vp, _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_float]),
     "cdwac_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
@@ -109,6 +114,25 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def freq_decomposition(freq, dmin: float, dmax: float, tol: float):
+    """Host-only decomposition of the imaginary-axis weights (cdwac_freq_decomposition):
+    returns (skel, rest, T) with c_rest[r] ~= sum_s T[r, s] c_skel[s]."""
+    lib = load_library()
+    w = np.ascontiguousarray(freq, np.float64)
+    n = len(w)
+    ns = ctypes.c_int32(0)
+    skel = np.zeros(n, np.int32)
+    rest = np.zeros(n, np.int32)
+    T = np.zeros(n * n, np.float64)
+    rc = lib.cdwac_freq_decomposition(n, _np_ptr(w, ctypes.c_double), float(dmin), float(dmax), float(tol),
+                                      ctypes.byref(ns), _np_ptr(skel, ctypes.c_int32),
+                                      _np_ptr(rest, ctypes.c_int32), _np_ptr(T, ctypes.c_double))
+    if rc != 0:
+        raise ValueError(f"cdwac_freq_decomposition failed ({rc})")
+    k = ns.value
+    return skel[:k].copy(), rest[:n - k].copy(), T[:(n - k) * k].reshape(n - k, k).copy()
 
 
 def header_functions(path: str = HEADER):
@@ -209,7 +233,7 @@ class Cdwac:
     @staticmethod
     def make_params(freq, weight, ref_im_idx, ref_re, win_lo, win_hi, eta=1e-3, eta_ref=1e-3,
                     pade_tol=1e-9, qp_tol=1e-10, qp_maxit=100, prec="p64", use_mlp_seed=False,
-                    mlp_accept=0.0):
+                    mlp_accept=0.0, freq_rank_tol=0.0):
         arrs = dict(freq=np.ascontiguousarray(freq, np.float64),
                     weight=np.ascontiguousarray(weight, np.float64),
                     ref_im=np.ascontiguousarray(ref_im_idx, np.int32),
@@ -224,7 +248,8 @@ class Cdwac:
                         win_lo=_np_ptr(arrs["lo"], ctypes.c_double),
                         win_hi=_np_ptr(arrs["hi"], ctypes.c_double), qp_tol=qp_tol,
                         qp_maxit=qp_maxit, prec=PREC[prec] if isinstance(prec, str) else int(prec),
-                        use_mlp_seed=int(bool(use_mlp_seed)), mlp_accept=mlp_accept)
+                        use_mlp_seed=int(bool(use_mlp_seed)), mlp_accept=mlp_accept,
+                        freq_rank_tol=freq_rank_tol)
         return p, arrs
 
     # -- entry points -----------------------------------------------------

@@ -35,6 +35,7 @@ struct Plan {
     // sizes
     int n_mo, n_occ, n_virt, n_aux, S, n_freq, n_im, n_re, n_pts, n_f, prec;
     int npad, cpad, cfpad, ni, n_fit, nblk, nb, n_tpi, n_tw, n_twf;
+    int n_comp;   // planes computed by the contraction (all, or skeleton + near-real)
     int64_t K, kpad;
     // persistent regions
     Region eps, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
@@ -42,7 +43,7 @@ struct Plan {
     // transient regions (prepare only)
     Region zr, zi, part, idflag, amax, sf, cw, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
         bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w, x32, yh, yl, t_pi, t_w,
-        t_wf;
+        t_wf, pmap, skel, rest, tmat;
     size_t total = 0;
 };
 
@@ -182,6 +183,8 @@ int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p
     if (p->prec < CDWAC_P64 || p->prec > CDWAC_F16X3) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", p->prec);
     if (p->use_mlp_seed != 0 && p->use_mlp_seed != 1) return fail(ctx, CDWAC_EINVAL, "use_mlp_seed must be 0 or 1");
     if (p->use_mlp_seed && !(p->mlp_accept >= 0.0)) return fail(ctx, CDWAC_EINVAL, "mlp_accept must be >= 0");
+    if (!(p->freq_rank_tol >= 0.0 && p->freq_rank_tol < 1.0))
+        return fail(ctx, CDWAC_EINVAL, "freq_rank_tol must be in [0, 1)");
     return CDWAC_OK;
 }
 
@@ -190,6 +193,103 @@ int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p
 void fit_range(const double* eps, int n_mo, int n_occ, double lo, double hi, int& m0, int& m1) {
     m0 = (int)(std::lower_bound(eps, eps + n_occ, lo) - eps);
     m1 = n_occ + (int)(std::upper_bound(eps + n_occ, eps + n_mo, hi) - (eps + n_occ));
+}
+
+// ---- frequency decomposition of the imaginary-axis polarizabilities -------
+// On the imaginary axis Pi(i w_f) = X diag(c_f) X^T with
+// c_f(D) = -2 s D / (w_f^2 + D^2), a smooth family of functions of the
+// transition energy D in [dmin, dmax].  A row interpolative decomposition of
+// that family, c_f ~= sum_{s in S} T[f][s] c_s, gives
+// Pi(i w_f) ~= sum_s T[f][s] Pi(i w_s), so only the skeleton planes S need the
+// rank-K contraction.  The decomposition is taken on a logarithmic grid of
+// D (the weights vary on the scale of D itself) by column-pivoted
+// Gram-Schmidt with re-orthogonalisation; the rank is the smallest for which
+// the sup-norm error of every interpolated function on the grid is at most
+// tol times that function's maximum.  Returns false if no rank below n meets
+// tol (then every plane is computed).
+struct FreqId {
+    std::vector<int> skel, rest;
+    std::vector<double> T;   // [rest.size()][skel.size()], for the unscaled weights
+};
+
+bool freq_id(const double* w, int n, double dmin, double dmax, double tol, FreqId& out) {
+    const int m = 2048;
+    std::vector<double> G((size_t)m * n), A, scale(n, 0.0);
+    for (int f = 0; f < n; ++f) {
+        for (int j = 0; j < m; ++j) {
+            const double d = dmin * std::pow(dmax / dmin, (double)j / (m - 1));
+            const double g = d / (w[f] * w[f] + d * d);
+            G[(size_t)f * m + j] = g;
+            scale[f] = std::max(scale[f], g);
+        }
+        for (int j = 0; j < m; ++j) G[(size_t)f * m + j] /= scale[f];
+    }
+    A = G;
+    std::vector<int> piv(n);
+    for (int i = 0; i < n; ++i) piv[i] = i;
+    std::vector<double> R((size_t)n * n, 0.0);   // R[k * n + i], columns in pivot order
+    auto col = [&](int c) { return &A[(size_t)c * m]; };
+    int steps = 0;
+    for (int k = 0; k < n; ++k) {
+        int best = -1;
+        double bn = 0.0;
+        for (int i = k; i < n; ++i) {
+            const double* a = col(piv[i]);
+            double s2 = 0.0;
+            for (int j = 0; j < m; ++j) s2 += a[j] * a[j];
+            if (s2 > bn) { bn = s2; best = i; }
+        }
+        if (best < 0 || !(bn > 1e-300)) break;
+        std::swap(piv[k], piv[best]);
+        // R columns already computed for rows < k follow the swap
+        for (int r = 0; r < k; ++r) std::swap(R[(size_t)r * n + k], R[(size_t)r * n + best]);
+        double* q = col(piv[k]);
+        const double nq = std::sqrt(bn);
+        for (int j = 0; j < m; ++j) q[j] /= nq;
+        R[(size_t)k * n + k] = nq;
+        for (int i = k + 1; i < n; ++i) {
+            double* a = col(piv[i]);
+            double tot = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                double d = 0.0;
+                for (int j = 0; j < m; ++j) d += q[j] * a[j];
+                for (int j = 0; j < m; ++j) a[j] -= d * q[j];
+                tot += d;
+            }
+            R[(size_t)k * n + i] = tot;
+        }
+        steps = k + 1;
+    }
+    // smallest rank k whose interpolation error meets tol on the grid
+    for (int k = 1; k < steps; ++k) {
+        const int nr = n - k;
+        std::vector<double> T((size_t)nr * k);
+        double worst = 0.0;
+        for (int i = k; i < n && worst <= tol; ++i) {
+            double* t = &T[(size_t)(i - k) * k];
+            for (int r = k - 1; r >= 0; --r) {   // R11 t = R12(:, i)
+                double v = R[(size_t)r * n + i];
+                for (int c = r + 1; c < k; ++c) v -= R[(size_t)r * n + c] * t[c];
+                t[r] = v / R[(size_t)r * n + r];
+            }
+            const double* g = &G[(size_t)piv[i] * m];
+            for (int j = 0; j < m; ++j) {
+                double v = g[j];
+                for (int c = 0; c < k; ++c) v -= t[c] * G[(size_t)piv[c] * m + j];
+                worst = std::max(worst, std::fabs(v));
+            }
+        }
+        if (worst <= tol) {
+            out.skel.assign(piv.begin(), piv.begin() + k);
+            out.rest.assign(piv.begin() + k, piv.end());
+            out.T.assign((size_t)nr * k, 0.0);
+            for (int r = 0; r < nr; ++r)
+                for (int c = 0; c < k; ++c)
+                    out.T[(size_t)r * k + c] = T[(size_t)r * k + c] * scale[out.rest[r]] / scale[out.skel[c]];
+            return true;
+        }
+    }
+    return false;
 }
 
 Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
@@ -204,6 +304,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     P.n_re = p->n_ref_re;
     P.n_pts = P.n_im + P.n_re;
     P.n_f = P.n_freq + 2 * P.n_re;
+    P.n_comp = P.n_f;
     P.prec = p->prec;
     P.K = (int64_t)P.n_occ * P.n_virt;
     P.kpad = round_up(P.K, 32);
@@ -261,6 +362,10 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     add(P, P.zi, sizeof(double) * P.n_f);
     add(P, P.part, sizeof(int) * P.n_f);
     add(P, P.idflag, sizeof(int) * P.n_f);
+    add(P, P.pmap, sizeof(int) * P.n_f);
+    add(P, P.skel, sizeof(int) * P.n_freq);
+    add(P, P.rest, sizeof(int) * P.n_freq);
+    add(P, P.tmat, sizeof(double) * (size_t)P.n_freq * P.n_freq);
     // operand maxima: [0] |O^ia|, [1] |O^nm|, [2..2+F) |c_f|, [2+F..2+2F) |Lambda_f|
     add(P, P.amax, sizeof(uint32_t) * (2 + 2 * (size_t)P.n_f));
     // scales: [0] x, [1] B, cfac[F], pi_unscale[F], lam_scale[F], w_unscale[F]
@@ -551,6 +656,31 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     TRY(upload(ctx, at<double>(ctx, P.zi), zi.data(), P.n_f));
     TRY(upload(ctx, at<int>(ctx, P.part), part.data(), P.n_f));
     TRY(upload(ctx, at<int>(ctx, P.idflag), idf.data(), P.n_f));
+    // planes computed by the contraction: every plane, or the skeleton of the
+    // imaginary nodes plus the near-real planes (16-bit modes only)
+    FreqId fid;
+    bool use_id = false;
+    if (P.prec != CDWAC_P64 && prm->freq_rank_tol > 0.0 && P.n_freq >= 4) {
+        const double dmin = sys->eps[P.n_occ] - sys->eps[P.n_occ - 1];
+        const double dmax = sys->eps[P.n_mo - 1] - sys->eps[0];
+        use_id = freq_id(prm->freq, P.n_freq, dmin, dmax, prm->freq_rank_tol, fid);
+    }
+    std::vector<int> pmap;
+    if (use_id) {
+        pmap = fid.skel;
+        std::sort(pmap.begin(), pmap.end());
+    } else {
+        for (int f = 0; f < P.n_freq; ++f) pmap.push_back(f);
+    }
+    for (int f = P.n_freq; f < P.n_f; ++f) pmap.push_back(f);
+    P.n_comp = (int)pmap.size();
+    ctx->plan.n_comp = P.n_comp;
+    TRY(upload(ctx, at<int>(ctx, P.pmap), pmap.data(), pmap.size()));
+    if (use_id) {
+        TRY(upload(ctx, at<int>(ctx, P.skel), fid.skel.data(), fid.skel.size()));
+        TRY(upload(ctx, at<int>(ctx, P.rest), fid.rest.data(), fid.rest.size()));
+        TRY(upload(ctx, at<double>(ctx, P.tmat), fid.T.data(), fid.T.size()));
+    }
     int* err = at<int>(ctx, P.err);
     HIPCK(hipMemsetAsync(err, 0, sizeof(int) * 4, st));
     for (double& x : ctx->stage_ms) x = 0.0;
@@ -594,17 +724,25 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
         LAUNCHCK();
         TRY(seg_end(ctx));
     } else {
-        for (int f0 = 0; f0 < P.n_f; f0 += P.nb) {
-            const int nfb = std::min(P.nb, P.n_f - f0);
+        const int* pm = at<int>(ctx, P.pmap);
+        for (int f0 = 0; f0 < P.n_comp; f0 += P.nb) {
+            const int nfb = std::min(P.nb, P.n_comp - f0);
             TRY(seg_begin(ctx, 7));
-            launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, f0, nfb,
+            launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, pm + f0, nfb,
                             at<uint16_t>(ctx, P.yh), at<uint16_t>(ctx, P.yl));
             LAUNCHCK();
             TRY(seg_end(ctx));
             TRY(seg_begin(ctx, 1));
-            launch_pi_gemm(st, P.prec, P.npad, P.kpad, f0, nfb, at<uint16_t>(ctx, P.xh), at<uint16_t>(ctx, P.xl),
+            launch_pi_gemm(st, P.prec, P.npad, P.kpad, pm + f0, nfb, at<uint16_t>(ctx, P.xh), at<uint16_t>(ctx, P.xl),
                            at<uint16_t>(ctx, P.yh), at<uint16_t>(ctx, P.yl), at<int2>(ctx, P.t_pi), P.n_tpi, pi_unscale,
                            at<int>(ctx, P.idflag), at<double>(ctx, P.E));
+            LAUNCHCK();
+            TRY(seg_end(ctx));
+        }
+        if (use_id) {
+            TRY(seg_begin(ctx, 7));
+            launch_combine_planes(st, at<double>(ctx, P.E), P.npad, (int)fid.skel.size(), at<int>(ctx, P.skel),
+                                  (int)fid.rest.size(), at<int>(ctx, P.rest), at<double>(ctx, P.tmat));
             LAUNCHCK();
             TRY(seg_end(ctx));
         }
@@ -803,6 +941,9 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
            o_y = take(f64 ? 0 : 4 * (size_t)nf * npad * kpad), o_E = take(sizeof(double) * (size_t)nf * npad * npad);
     const std::vector<int2> tiles = f64 ? std::vector<int2>() : pi_tiles(npad);
     size_t o_t = take(sizeof(int2) * std::max<size_t>(1, tiles.size()));
+    size_t o_map = take(sizeof(int) * nf);
+    std::vector<int> fmap(nf);
+    for (int f = 0; f < nf; ++f) fmap[f] = f;
     char* buf = nullptr;
     if (hipMalloc(&buf, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -838,14 +979,16 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
                           (double*)(buf + o_E));
         } else {
             const int et = prec_elem(prec);
-            if (hipMemcpyAsync(buf + o_t, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st)) {
+            if (hipMemcpyAsync(buf + o_t, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st) ||
+                hipMemcpyAsync(buf + o_map, fmap.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st)) {
                 rc = fail(ctx, CDWAC_EHIP, "upload failed");
                 break;
             }
             launch_scales_pi(st, amax, nf, sf);
             launch_split_panel(st, et, sys->o_ia, 0, 1, K, sys->n_aux, K, sf, xh, xl, x32, npad, kpad);
-            launch_prescale(st, et, x32, npad, kpad, (float*)(buf + o_cw), sf + 2, 0, nf, yh, yl);
-            launch_pi_gemm(st, prec, npad, kpad, 0, nf, xh, xl, yh, yl, (int2*)(buf + o_t), (int)tiles.size(),
+            launch_prescale(st, et, x32, npad, kpad, (float*)(buf + o_cw), sf + 2, (int*)(buf + o_map), nf, yh, yl);
+            launch_pi_gemm(st, prec, npad, kpad, (int*)(buf + o_map), nf, xh, xl, yh, yl, (int2*)(buf + o_t),
+                           (int)tiles.size(),
                            sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));
         }
         if (hipGetLastError() != hipSuccess) {
@@ -907,6 +1050,25 @@ int cdwac_set_timing(cdwac_ctx* ctx, int on) {
 int cdwac_get_timing(const cdwac_ctx* ctx, double* ms, int32_t n) {
     if (!ctx || !ms || n < 0) return CDWAC_EINVAL;
     for (int i = 0; i < n && i < CDWAC_N_STAGES; ++i) ms[i] = ctx->stage_ms[i];
+    return CDWAC_OK;
+}
+
+int cdwac_freq_decomposition(int32_t n_freq, const double* freq, double dmin, double dmax, double tol,
+                             int32_t* n_skel, int32_t* skel, int32_t* rest, double* T) {
+    if (n_freq < 1 || !freq || !n_skel || !skel || !rest || !T) return CDWAC_EINVAL;
+    if (!(dmin > 0.0) || !(dmax > dmin) || !std::isfinite(dmax) || !(tol > 0.0 && tol < 1.0)) return CDWAC_EINVAL;
+    for (int f = 0; f < n_freq; ++f)
+        if (!(freq[f] > 0.0) || !std::isfinite(freq[f])) return CDWAC_EINVAL;
+    FreqId fid;
+    if (!freq_id(freq, n_freq, dmin, dmax, tol, fid)) {
+        *n_skel = n_freq;
+        for (int f = 0; f < n_freq; ++f) skel[f] = f;
+        return CDWAC_OK;
+    }
+    *n_skel = (int32_t)fid.skel.size();
+    std::copy(fid.skel.begin(), fid.skel.end(), skel);
+    std::copy(fid.rest.begin(), fid.rest.end(), rest);
+    std::copy(fid.T.begin(), fid.T.end(), T);
     return CDWAC_OK;
 }
 

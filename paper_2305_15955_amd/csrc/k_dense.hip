@@ -289,13 +289,15 @@ __device__ inline int out_row(int w, int bi, int lane, int v) {
 }
 __device__ inline int out_col(int w, int bj, int lane) { return (w & 1) * 128 + bj * 32 + (lane & 31); }
 
-// eps_f = delta_f I - Pi_f for the listed tiles of batch f (B = prescaled Y_f).
+// eps_f = delta_f I - Pi_f for the listed tiles of the planes f = fmap[fb]
+// (B = prescaled Y_f, batch slot fb).
 template <int ET, bool SPLIT>
 __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __restrict__ xh,
                                                           const uint16_t* __restrict__ xl,
                                                           const uint16_t* __restrict__ yh,
                                                           const uint16_t* __restrict__ yl, int64_t kpad,
-                                                          const int2* __restrict__ tiles, int n_tiles, int f0,
+                                                          const int2* __restrict__ tiles, int n_tiles,
+                                                          const int* __restrict__ fmap,
                                                           const double* __restrict__ pi_unscale,
                                                           const int* __restrict__ idflag, double* __restrict__ E,
                                                           int npad) {
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fb = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
-    const int I = tile.x, J = tile.y, f = f0 + fb;
+    const int I = tile.x, J = tile.y, f = fmap[fb];
     const int64_t ao = (int64_t)I * GT * kpad;
     const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GT * kpad;
     v16f acc[2][4];
@@ -403,18 +405,18 @@ void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double*
     hipLaunchKernelGGL(k_pi_f64, dim3(T * n_f), dim3(256), 0, s, x64, kpad, cw64, idflag, E, npad, n_f);
 }
 
-void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, int f0, int nfb, const uint16_t* xh,
+void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* fmap, int nfb, const uint16_t* xh,
                     const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* tiles, int n_tiles,
                     const double* pi_unscale, const int* idflag, double* E) {
     dim3 g(n_tiles * nfb), b(kGemmThreads);
     if (prec == PREC_B16X3)
-        hipLaunchKernelGGL((k_pi_gemm<0, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, f0, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<0, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
                            idflag, E, npad);
     else if (prec == PREC_B16)
-        hipLaunchKernelGGL((k_pi_gemm<0, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, f0, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<0, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
                            idflag, E, npad);
     else
-        hipLaunchKernelGGL((k_pi_gemm<1, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, f0, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<1, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
                            idflag, E, npad);
 }
 

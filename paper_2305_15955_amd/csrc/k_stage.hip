@@ -99,7 +99,7 @@ __global__ void k_scales_pi(const uint32_t* __restrict__ amax, int n_f, double* 
     }
 }
 
-// Y_f = split(X diag(c_f) * ys[f]) for the weight vectors f0 .. f0+nfb-1 as
+// Y_f = split(X diag(c_f) * ys[f]) for the weight vectors f = fmap[0 .. nfb) as
 // hi/lo panel planes [fb][npad][kpad] (layout of panel_off), from the FP32
 // row-major copy of X (zero padded).  One lane per row and 32-element k span:
 // it reads one 128-byte line of X once and, for every plane of the batch, the
@@ -107,8 +107,8 @@ __global__ void k_scales_pi(const uint32_t* __restrict__ amax, int n_f, double* 
 // of a wave write 1 KiB runs.
 template <int ET>
 __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad, const float* __restrict__ cw32,
-                           const double* __restrict__ ys, int f0, int nfb, uint16_t* __restrict__ yh,
-                           uint16_t* __restrict__ yl) {
+                           const double* __restrict__ ys, const int* __restrict__ fmap, int nfb,
+                           uint16_t* __restrict__ yh, uint16_t* __restrict__ yl) {
     const int lane = threadIdx.x & 63;
     const int64_t ks = kpad / 32, kw = kpad / 8;
     const int64_t nspan = (int64_t)(npad / 64) * ks;
@@ -121,7 +121,7 @@ __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad
 #pragma unroll
         for (int q = 0; q < 8; ++q) x[q] = xr[q];
         for (int fb = 0; fb < nfb; ++fb) {
-            const int f = f0 + fb;
+            const int f = fmap[fb];
             const float s = (float)ys[f];
             const float4* cr = reinterpret_cast<const float4*>(cw32 + (int64_t)f * kpad + sp * 32);
             uint4* oh = reinterpret_cast<uint4*>(yh + fb * plane);
@@ -366,6 +366,42 @@ __global__ void k_extract_pi(const double* __restrict__ E, int npad, int n, int 
     out[t] = -E[(int64_t)(2 * j + q) * npad * npad + (int64_t)a * npad + b];
 }
 
+
+// Planes that the frequency decomposition does not compute:
+//   E_f = sum_s T[r][s] E_{skel[s]} + (1 - sum_s T[r][s]) I,  f = rest[r],
+// which is eps_f = I - Pi_f with Pi_f = sum_s T[r][s] Pi_{skel[s]}.  Lower
+// triangle only; one block per 128 columns of one row.
+constexpr int kCombThreads = 128, kCombMax = 64;
+__global__ __launch_bounds__(kCombThreads) void k_combine_planes(double* __restrict__ E, int npad, int k,
+                                                                 const int* __restrict__ skel, int n_rest,
+                                                                 const int* __restrict__ rest,
+                                                                 const double* __restrict__ T) {
+    __shared__ double sv[kCombMax][kCombThreads];
+    __shared__ double st[kCombMax * kCombMax];
+    __shared__ double sd[kCombMax];
+    const int P = blockIdx.y, q0 = blockIdx.x * kCombThreads;
+    if (q0 > P) return;
+    const int t = threadIdx.x;
+    for (int i = t; i < n_rest * k; i += kCombThreads) st[i] = T[i];
+    __syncthreads();
+    if (t < n_rest) {
+        double a = 1.0;
+        for (int s = 0; s < k; ++s) a -= st[t * k + s];
+        sd[t] = a;
+    }
+    const int Q = q0 + t;
+    const bool ok = Q <= P;
+    const int64_t n2 = (int64_t)npad * npad, o = (int64_t)P * npad + Q;
+    for (int s = 0; s < k; ++s) sv[s][t] = ok ? E[(int64_t)skel[s] * n2 + o] : 0.0;
+    __syncthreads();
+    if (!ok) return;
+    for (int r = 0; r < n_rest; ++r) {
+        double a = P == Q ? sd[r] : 0.0;
+        for (int s = 0; s < k; ++s) a += st[r * k + s] * sv[s][t];
+        E[(int64_t)rest[r] * n2 + o] = a;
+    }
+}
+
 // ============================================================================
 // Host launchers
 // ============================================================================
@@ -388,13 +424,13 @@ void launch_scales_pi(hipStream_t s, const uint32_t* amax, int n_f, double* sf) 
 }
 
 void launch_prescale(hipStream_t s, int et, const float* x32, int npad, int64_t kpad, const float* cw32,
-                     const double* ys, int f0, int nfb, uint16_t* yh, uint16_t* yl) {
+                     const double* ys, const int* fmap, int nfb, uint16_t* yh, uint16_t* yl) {
     const int64_t waves = (int64_t)(npad / 64) * (kpad / 32);
     dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 8192)));
     if (et == 1)
-        hipLaunchKernelGGL(k_prescale<1>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, nfb, yh, yl);
+        hipLaunchKernelGGL(k_prescale<1>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, fmap, nfb, yh, yl);
     else
-        hipLaunchKernelGGL(k_prescale<0>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, f0, nfb, yh, yl);
+        hipLaunchKernelGGL(k_prescale<0>, grid, dim3(256), 0, s, x32, npad, kpad, cw32, ys, fmap, nfb, yh, yl);
 }
 
 void launch_scales_w(hipStream_t s, const uint32_t* lmax, int n_f, double* sf, double* lam_scale, double* w_unscale) {
@@ -439,6 +475,13 @@ void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, i
 void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax) {
     int nt = npad / 32, T = nt * (nt + 1) / 2;
     hipLaunchKernelGGL(k_finalize_lambda, dim3(T * n_f), dim3(256), 0, s, E, npad, idflag, lmax);
+}
+
+void launch_combine_planes(hipStream_t s, double* E, int npad, int k, const int* skel, int n_rest, const int* rest,
+                           const double* T) {
+    if (n_rest <= 0) return;
+    dim3 grid((unsigned)((npad + kCombThreads - 1) / kCombThreads), (unsigned)npad);
+    hipLaunchKernelGGL(k_combine_planes, grid, dim3(kCombThreads), 0, s, E, npad, k, skel, n_rest, rest, T);
 }
 
 void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out) {

@@ -55,7 +55,7 @@ void launch_weights(hipStream_t s, const double* eps, int n_occ, int n_virt, dou
                     uint32_t* cmax);
 void launch_scales_pi(hipStream_t s, const uint32_t* amax, int n_f, double* sf);
 void launch_prescale(hipStream_t s, int et, const float* x32, int npad, int64_t kpad, const float* cw32,
-                     const double* ys, int f0, int nfb, uint16_t* yh, uint16_t* yl);
+                     const double* ys, const int* fmap, int nfb, uint16_t* yh, uint16_t* yl);
 void launch_scales_w(hipStream_t s, const uint32_t* lmax, int n_f, double* sf, double* lam_scale, double* w_unscale);
 void launch_pad_f64(hipStream_t s, const double* src, int64_t lds, int rows, int64_t cols, double* f64, int rpad,
                     int64_t cpad);
@@ -68,6 +68,8 @@ void launch_transpose_b(hipStream_t s, int et, const double* onm, int S, int N, 
                         int npad, uint32_t* bmax, int* err);
 void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, int n_occ, double* sx);
 void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax);
+void launch_combine_planes(hipStream_t s, double* E, int npad, int k, const int* skel, int n_rest, const int* rest,
+                           const double* T);
 void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out);
 void launch_reduce_w(hipStream_t s, const double* partial_im, const double* partial_re, int ni, int cpad,
                      int cfpad, int n_im, int n_re, int ncols, int nfit, double* w_im, double* w_re);
@@ -79,7 +81,7 @@ std::vector<int2> pi_tiles(int npad);
 std::vector<int2> w_tiles(int npad, int cpad);
 void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double* x64, const double* cw64,
                    const int* idflag, double* E);
-void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, int f0, int nfb, const uint16_t* xh,
+void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* fmap, int nfb, const uint16_t* xh,
                     const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* tiles, int n_tiles,
                     const double* pi_unscale, const int* idflag, double* E);
 int w_partial_blocks(int prec, int npad);
