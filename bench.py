@@ -8,7 +8,8 @@ every core state.  Inputs (KS energies, RI coefficients) are seeded synthetic
 arrays already resident in HBM when the timed region starts.
 
 Prints one JSON line.  value = core QP energies per second of the whole job
-(reduced-precision contractions, learned seed if a model is installed);
+(fp16 polarizability, fp16-split W, FP64 elsewhere, skeleton imaginary
+nodes, learned seed if a model is installed);
 also reported: the plain FP64 GPU path, the per-state error of the reduced
 path against it in meV, per-stage times from HIP events on the library's
 stream, the roofline of the polarizability kernel, and the FP64 oracle timed
@@ -28,8 +29,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f16x3": 2.5e15, "b16x3": 2.5e15, "b16": 2.5e15, "p64": 78.6e12}   # dense MFMA, FLOP/s
-PRODUCTS = {"f16x3": 3, "b16x3": 3, "b16": 1, "p64": 1}
+PEAK = {"f16": 2.5e15, "f16x3": 2.5e15, "b16x3": 2.5e15, "b16": 2.5e15, "p64": 78.6e12}   # dense MFMA, FLOP/s
+PRODUCTS = {"f16": 1, "f16x3": 3, "b16x3": 3, "b16": 1, "p64": 1}      # matrix-core products per MAC of Pi
+DTYPE = {"f16": "f16 (Pi) + f16x3 (W) + f64", "f16x3": "f16x3 + f64", "b16x3": "bf16x3 + f64",
+         "b16": "bf16 + f64", "p64": "f64"}
 MODEL_PATH = os.path.join(ROOT, "paper_2305_15955_amd", "seed_model.npz")
 
 
@@ -43,7 +46,7 @@ def measured_traffic(prec, workload):
     the summary is for another kernel source or configuration."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_pi_gemm_{workload}_hbm_traffic.md")
-    if prec != "f16x3" or not os.path.exists(path):
+    if prec != "f16" or not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
@@ -102,7 +105,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="precision_naux5000")
-    ap.add_argument("--prec", default="f16x3", choices=["f16x3", "b16x3", "b16", "p64"])
+    ap.add_argument("--prec", default="f16", choices=["f16", "f16x3", "b16x3", "b16", "p64"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 GPU path")
     ap.add_argument("--rank-tol", type=float, default=1e-10,
                     help="imaginary-node decomposition tolerance of the 16-bit path (0: every node)")
@@ -166,7 +169,7 @@ def main():
     res = {"metric": "core QP energies/sec at N_aux=5000 (mixed+MLP vs FP64), meV err, MFMA util",
            "value": qps, "unit": "core QP energies/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": f"{args.prec}+fp64",
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.prec],
            "data": "synthetic (seeded Gaussian RI coefficients, no molecule)",
            "config": {"workload": args.workload, "n_aux": s.n_aux, "n_mo": s.n_mo, "n_occ": s.n_occ,
                       "n_states": s.n_states, "n_freq": len(freq), "n_pade": len(ref_im) + len(ref_re),

@@ -56,8 +56,11 @@ typedef enum {
     CDWAC_P64 = 0,       /* FP64 matrix cores                                        */
     CDWAC_B16X3 = 1,     /* bf16 hi/lo split (16-bit significands), 3 products       */
     CDWAC_B16 = 2,       /* plain bf16, one product (accuracy ablation only)         */
-    CDWAC_F16X3 = 3      /* fp16 hi/lo split of power-of-two-scaled operands (22-bit
+    CDWAC_F16X3 = 3,     /* fp16 hi/lo split of power-of-two-scaled operands (22-bit
                             significands), 3 products; same matrix-core rate as bf16 */
+    CDWAC_F16 = 4        /* Pi: plain fp16 of the scaled operands, one product (its
+                            K-term sums average the operand rounding out); W: the
+                            fp16 split of CDWAC_F16X3                                */
 } cdwac_prec;
 /* Every 16-bit mode accumulates in FP32 in the matrix cores over the whole
  * contraction; the sums are converted to FP64 at the end. */

@@ -24,10 +24,10 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cdwac.h")
 
 CDWAC_OK, CDWAC_EINVAL, CDWAC_ENOMEM, CDWAC_EHIP, CDWAC_ENOTPD, CDWAC_ESTATE = 0, -1, -2, -3, -4, -5
 CDWAC_WNOROOT = 1
-CDWAC_P64, CDWAC_B16X3, CDWAC_B16, CDWAC_F16X3 = 0, 1, 2, 3
+CDWAC_P64, CDWAC_B16X3, CDWAC_B16, CDWAC_F16X3, CDWAC_F16 = 0, 1, 2, 3, 4
 FLAG_NOROOT, FLAG_FALLBACK, FLAG_MLP_ACCEPTED = 1, 2, 4
 MLP_NPARAM = 4801
-PREC = {"p64": CDWAC_P64, "b16x3": CDWAC_B16X3, "b16": CDWAC_B16, "f16x3": CDWAC_F16X3}
+PREC = {"p64": CDWAC_P64, "b16x3": CDWAC_B16X3, "b16": CDWAC_B16, "f16x3": CDWAC_F16X3, "f16": CDWAC_F16}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

@@ -180,7 +180,7 @@ int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p
         if (!std::isfinite(p->win_lo[j]) || !std::isfinite(p->win_hi[j]) || !(p->win_lo[j] < p->win_hi[j]))
             return fail(ctx, CDWAC_EINVAL, "QP window %d must satisfy lo < hi", j);
     if (!(p->qp_tol > 0.0) || p->qp_maxit < 1) return fail(ctx, CDWAC_EINVAL, "qp_tol > 0 and qp_maxit >= 1 required");
-    if (p->prec < CDWAC_P64 || p->prec > CDWAC_F16X3) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", p->prec);
+    if (p->prec < CDWAC_P64 || p->prec > CDWAC_F16) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", p->prec);
     if (p->use_mlp_seed != 0 && p->use_mlp_seed != 1) return fail(ctx, CDWAC_EINVAL, "use_mlp_seed must be 0 or 1");
     if (p->use_mlp_seed && !(p->mlp_accept >= 0.0)) return fail(ctx, CDWAC_EINVAL, "mlp_accept must be >= 0");
     if (!(p->freq_rank_tol >= 0.0 && p->freq_rank_tol < 1.0))
@@ -374,14 +374,16 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     if (f64) {
         add(P, P.x64, sizeof(double) * (size_t)P.npad * P.kpad);
     } else {
+        // one-product Pi (CDWAC_F16) needs no lo planes of X and Y
+        const size_t n_pl = P.prec == CDWAC_F16 ? 1 : 2;
         add(P, P.xh, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
-        add(P, P.xl, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
+        add(P, P.xl, n_pl == 2 ? sizeof(uint16_t) * (size_t)P.npad * P.kpad : 0);
         add(P, P.x32, sizeof(float) * (size_t)P.npad * P.kpad);
         // prescaled operands X diag(c_f) for a batch of nb weight vectors
         const size_t per_f = sizeof(uint16_t) * (size_t)P.npad * P.kpad;
-        P.nb = (int)std::max<size_t>(1, std::min<size_t>(P.n_f, kPrescaleBudget / (2 * per_f)));
+        P.nb = (int)std::max<size_t>(1, std::min<size_t>(P.n_f, kPrescaleBudget / (n_pl * per_f)));
         add(P, P.yh, per_f * P.nb);
-        add(P, P.yl, per_f * P.nb);
+        add(P, P.yl, n_pl == 2 ? per_f * P.nb : 0);
         P.n_tpi = (int)pi_tiles(P.npad).size();
         P.n_tw = (int)w_tiles(P.npad, P.cpad).size();
         P.n_twf = (int)w_tiles(P.npad, P.cfpad).size();
@@ -691,6 +693,7 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     // (a0) staging: weights, operand maxima and scales, the O^{ia} operand
     TRY(seg_begin(ctx, 0));
     const int et = prec_elem(P.prec);
+    const bool pi_split = P.prec != CDWAC_F16;
     uint32_t* amax = at<uint32_t>(ctx, P.amax);
     double* sf = at<double>(ctx, P.sf);
     double* pi_unscale = sf + 2 + P.n_f;
@@ -708,7 +711,7 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     } else {
         launch_scales_pi(st, amax, P.n_f, sf);
         launch_split_panel(st, et, sys->o_ia, 0, 1, P.K, P.n_aux, P.K, sf, at<uint16_t>(ctx, P.xh),
-                           at<uint16_t>(ctx, P.xl), at<float>(ctx, P.x32), P.npad, P.kpad);
+                           pi_split ? at<uint16_t>(ctx, P.xl) : nullptr, at<float>(ctx, P.x32), P.npad, P.kpad);
         std::vector<int2> tp = pi_tiles(P.npad), tw = w_tiles(P.npad, P.cpad), twf = w_tiles(P.npad, P.cfpad);
         TRY(upload(ctx, at<int2>(ctx, P.t_pi), tp.data(), tp.size()));
         TRY(upload(ctx, at<int2>(ctx, P.t_w), tw.data(), tw.size()));
@@ -729,12 +732,13 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
             const int nfb = std::min(P.nb, P.n_comp - f0);
             TRY(seg_begin(ctx, 7));
             launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, pm + f0, nfb,
-                            at<uint16_t>(ctx, P.yh), at<uint16_t>(ctx, P.yl));
+                            at<uint16_t>(ctx, P.yh), pi_split ? at<uint16_t>(ctx, P.yl) : nullptr);
             LAUNCHCK();
             TRY(seg_end(ctx));
             TRY(seg_begin(ctx, 1));
-            launch_pi_gemm(st, P.prec, P.npad, P.kpad, pm + f0, nfb, at<uint16_t>(ctx, P.xh), at<uint16_t>(ctx, P.xl),
-                           at<uint16_t>(ctx, P.yh), at<uint16_t>(ctx, P.yl), at<int2>(ctx, P.t_pi), P.n_tpi, pi_unscale,
+            launch_pi_gemm(st, P.prec, P.npad, P.kpad, pm + f0, nfb, at<uint16_t>(ctx, P.xh),
+                           at<uint16_t>(ctx, pi_split ? P.xl : P.xh), at<uint16_t>(ctx, P.yh),
+                           at<uint16_t>(ctx, pi_split ? P.yl : P.yh), at<int2>(ctx, P.t_pi), P.n_tpi, pi_unscale,
                            at<int>(ctx, P.idflag), at<double>(ctx, P.E));
             LAUNCHCK();
             TRY(seg_end(ctx));
@@ -905,7 +909,7 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
                          const double* z_im, double* pi_re, double* pi_im) {
     if (!ctx) return CDWAC_EINVAL;
     TRY(validate_system(ctx, sys));
-    if (prec < CDWAC_P64 || prec > CDWAC_F16X3) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", prec);
+    if (prec < CDWAC_P64 || prec > CDWAC_F16) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", prec);
     if (n_z < 1 || !z_re || !z_im || !pi_re) return fail(ctx, CDWAC_EINVAL, "bad z list or output");
     bool all_imag = true;
     for (int j = 0; j < n_z; ++j) {
@@ -985,8 +989,11 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
                 break;
             }
             launch_scales_pi(st, amax, nf, sf);
-            launch_split_panel(st, et, sys->o_ia, 0, 1, K, sys->n_aux, K, sf, xh, xl, x32, npad, kpad);
-            launch_prescale(st, et, x32, npad, kpad, (float*)(buf + o_cw), sf + 2, (int*)(buf + o_map), nf, yh, yl);
+            const bool split = prec != CDWAC_F16;
+            launch_split_panel(st, et, sys->o_ia, 0, 1, K, sys->n_aux, K, sf, xh, split ? xl : nullptr, x32, npad,
+                               kpad);
+            launch_prescale(st, et, x32, npad, kpad, (float*)(buf + o_cw), sf + 2, (int*)(buf + o_map), nf, yh,
+                            split ? yl : nullptr);
             launch_pi_gemm(st, prec, npad, kpad, (int*)(buf + o_map), nf, xh, xl, yh, yl, (int2*)(buf + o_t),
                            (int)tiles.size(),
                            sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));

@@ -197,7 +197,10 @@ constexpr int GT = 256, GK = 32, KGR = GK / 8, NST = 2;
 constexpr int kGemmThreads = 512;
 constexpr int OP_STAGE = 2 * KGR * GT;          // uint4 slots of one operand per stage
 constexpr int STAGE = 2 * OP_STAGE;
-constexpr int kLoadsPerWave = 2 * 2 * KGR * 4 / 8;
+// 64-row-block loads per chunk: 2 operands x 2 planes x KGR k-groups x 4 row
+// blocks with the hi/lo split, the hi planes alone without it
+template <bool SPLIT>
+constexpr int loads_per_wave() { return (SPLIT ? 2 : 1) * 2 * KGR * 4 / 8; }
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -209,15 +212,19 @@ constexpr int wait_vm_lgkm0(int n) { return ((n >> 4) << 14) | (7 << 4) | (n & 1
 // flight for the next chunk.  Callers wait for what must be complete first.
 __device__ inline void stage_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// Issues this wave's share (8 of 64 row-block loads) of chunk k0 into stage st.
+// Issues this wave's share (8 of 64 row-block loads, 4 of 32 without the
+// split) of chunk k0 into stage st.
+template <bool SPLIT>
 __device__ inline void gemm_issue(uint4* lds, int st, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
                                   const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl, int64_t K,
                                   int64_t k0, int w, int lane) {
+    constexpr int per = loads_per_wave<SPLIT>();
 #pragma unroll
-    for (int q = 0; q < kLoadsPerWave; ++q) {
-        const int u = w * kLoadsPerWave + q;          // 0 .. 63
-        const int op = u >> 5, v = u & 31;            // operand A or B
-        const int pl = v >> 4, kg = (v >> 2) & 3, rb = v & 3;
+    for (int q = 0; q < per; ++q) {
+        const int u = w * per + q;
+        const int op = SPLIT ? u >> 5 : u >> 4;       // operand A or B
+        const int v = SPLIT ? u & 31 : u & 15;
+        const int pl = SPLIT ? v >> 4 : 0, kg = (v >> 2) & 3, rb = v & 3;
         const uint16_t* base = op ? (pl ? bl : bh) : (pl ? al : ah);
         const uint16_t* g = base + (int64_t)rb * 64 * K + (k0 + kg * 8) * 64 + lane * 8;
         const int slot = op * OP_STAGE + (pl * KGR + kg) * GT + rb * 64;
@@ -272,12 +279,12 @@ __device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, co
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v16f{};
-    gemm_issue(lds, 0, ah, al, bh, bl, K, 0, w, lane);
+    gemm_issue<SPLIT>(lds, 0, ah, al, bh, bl, K, 0, w, lane);
     for (int64_t i = 0; i < nk; ++i) {
         // chunk i has landed (own loads) and every wave is done with chunk i-1
         __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
         stage_barrier();
-        if (i + 1 < nk) gemm_issue(lds, (int)((i + 1) % NST), ah, al, bh, bl, K, (i + 1) * GK, w, lane);
+        if (i + 1 < nk) gemm_issue<SPLIT>(lds, (int)((i + 1) % NST), ah, al, bh, bl, K, (i + 1) * GK, w, lane);
         gemm_chunk<ET, SPLIT>(lds, (int)(i % NST), r0, c0, lane, acc);
     }
 }
@@ -414,6 +421,9 @@ void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* 
                            idflag, E, npad);
     else if (prec == PREC_B16)
         hipLaunchKernelGGL((k_pi_gemm<0, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
+                           idflag, E, npad);
+    else if (prec == PREC_F16)
+        hipLaunchKernelGGL((k_pi_gemm<1, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
                            idflag, E, npad);
     else
         hipLaunchKernelGGL((k_pi_gemm<1, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,

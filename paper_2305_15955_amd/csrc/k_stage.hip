@@ -104,7 +104,8 @@ __global__ void k_scales_pi(const uint32_t* __restrict__ amax, int n_f, double* 
 // row-major copy of X (zero padded).  One lane per row and 32-element k span:
 // it reads one 128-byte line of X once and, for every plane of the batch, the
 // matching line of c_f and four 16-byte words per output plane; the 64 lanes
-// of a wave write 1 KiB runs.
+// of a wave write 1 KiB runs.  yl == nullptr skips the lo planes (one-product
+// modes).
 template <int ET>
 __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad, const float* __restrict__ cw32,
                            const double* __restrict__ ys, const int* __restrict__ fmap, int nfb,
@@ -125,7 +126,7 @@ __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad
             const float s = (float)ys[f];
             const float4* cr = reinterpret_cast<const float4*>(cw32 + (int64_t)f * kpad + sp * 32);
             uint4* oh = reinterpret_cast<uint4*>(yh + fb * plane);
-            uint4* ol = reinterpret_cast<uint4*>(yl + fb * plane);
+            uint4* ol = yl ? reinterpret_cast<uint4*>(yl + fb * plane) : nullptr;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const float4 x0 = x[2 * g], x1 = x[2 * g + 1], c0 = cr[2 * g], c1 = cr[2 * g + 1];
@@ -142,7 +143,7 @@ __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad
                 }
                 const int64_t word = (rb * kw + sp * 4 + g) * 64 + lane;
                 oh[word] = make_uint4(h[0], h[1], h[2], h[3]);
-                ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
+                if (yl) ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
             }
         }
     }
@@ -179,7 +180,8 @@ __global__ void k_pad_f64(const double* __restrict__ src, int64_t lds, int rows,
 // Plane z = blockIdx.y of src (+ z * sstride; [rows][cols], leading dim lds)
 // times scale[z] -> hi/lo panel planes (+ z * rpad * cpad) [rpad][cpad], zero
 // padded, and for plane 0 optionally an unscaled FP32 row-major copy.  One
-// lane per row and 8-element k-group (one 16-byte word per plane).
+// lane per row and 8-element k-group (one 16-byte word per plane).  lo ==
+// nullptr skips the lo planes.
 template <int ET>
 __global__ void k_split_panel(const double* __restrict__ src, int64_t sstride, int64_t lds, int rows,
                               int64_t cols, const double* __restrict__ scale, uint16_t* __restrict__ hi,
@@ -190,7 +192,7 @@ __global__ void k_split_panel(const double* __restrict__ src, int64_t sstride, i
     const double s = scale ? scale[z] : 1.0;
     const double* sp = src + z * sstride;
     uint4* oh = reinterpret_cast<uint4*>(hi + (int64_t)z * rpad * cpad);
-    uint4* ol = reinterpret_cast<uint4*>(lo + (int64_t)z * rpad * cpad);
+    uint4* ol = lo ? reinterpret_cast<uint4*>(lo + (int64_t)z * rpad * cpad) : nullptr;
     const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < nw; w += wstride) {
         const int64_t rb = w / kw, g = w % kw;
@@ -215,7 +217,7 @@ __global__ void k_split_panel(const double* __restrict__ src, int64_t sstride, i
             l[e] = la | ((uint32_t)lb << 16);
         }
         oh[w * 64 + lane] = make_uint4(h[0], h[1], h[2], h[3]);
-        ol[w * 64 + lane] = make_uint4(l[0], l[1], l[2], l[3]);
+        if (lo) ol[w * 64 + lane] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 }
 

@@ -45,8 +45,8 @@ struct QpOut {
 };
 
 // precision codes (same values as cdwac_prec)
-constexpr int PREC_P64 = 0, PREC_B16X3 = 1, PREC_B16 = 2, PREC_F16X3 = 3;
-inline int prec_elem(int prec) { return prec == PREC_F16X3 ? 1 : 0; }
+constexpr int PREC_P64 = 0, PREC_B16X3 = 1, PREC_B16 = 2, PREC_F16X3 = 3, PREC_F16 = 4;
+inline int prec_elem(int prec) { return prec == PREC_F16X3 || prec == PREC_F16 ? 1 : 0; }
 
 // k_stage.hip
 void launch_absmax(hipStream_t s, const double* src, int64_t lds, int rows, int64_t cols, uint32_t* amax, int* err);

@@ -79,12 +79,12 @@ def test_acene_nmo600_against_stored_oracle(lib):
     np.testing.assert_allclose(got, want, rtol=SIGMA_RTOL)
     # reduced precision against the stored FP64 oracle, with every imaginary
     # node contracted and with the skeleton-node decomposition
-    for rank_tol in (0.0, 1e-10):
-        prepare(lib, case, "f16x3", sysc, rank_tol)
+    for prec, rank_tol in (("f16x3", 0.0), ("f16x3", 1e-10), ("f16", 1e-10)):
+        prepare(lib, case, prec, sysc, rank_tol)
         out = lib.cdwac_qp(s.n_states)
         d = [(out[n]["qp"] - g["qp"][n]) / MEV for n in range(s.n_states)]
-        print("f16x3 rank_tol", rank_tol, "vs oracle (meV)", np.round(d, 4))
-        assert max(abs(x) for x in d) <= 1.0, (rank_tol, d)
+        print(prec, "rank_tol", rank_tol, "vs oracle (meV)", np.round(d, 4))
+        assert max(abs(x) for x in d) <= 1.0, (prec, rank_tol, d)
 
 
 def test_naux5000_sampled_pi_and_properties(lib):
@@ -102,7 +102,7 @@ def test_naux5000_sampled_pi_and_properties(lib):
     # fp16 split: products exact to ~2^-22, but FP32 accumulation over
     # K / 16 = 19 532 matrix-core steps gives ~sqrt(19 532) * 2^-24 = 8e-6
     # relative to the largest partial sums
-    for prec, tol in (("p64", 1e-12), ("f16x3", 3e-5)):
+    for prec, tol in (("p64", 1e-12), ("f16x3", 3e-5), ("f16", 3e-5)):
         pis = lib.cdwac_polarizability(sysc, zs, prec=prec)
         for j, z in enumerate(zs):
             ref = R.polarizability_entries(s.o_ia, s.eps, s.n_occ, z, s.spin, pairs)
@@ -113,7 +113,7 @@ def test_naux5000_sampled_pi_and_properties(lib):
         del pis
     qp = {}
     evals = {}
-    for prec, rank_tol in (("f16x3", 0.0), ("f16x3r", 1e-10), ("p64", 0.0)):
+    for prec, rank_tol in (("f16x3", 0.0), ("f16x3r", 1e-10), ("f16r", 1e-10), ("p64", 0.0)):
         prepare(lib, case, prec.rstrip("r"), sysc, rank_tol)
         out = lib.cdwac_qp(s.n_states)
         qp[prec] = np.array([o["qp"] for o in out])
@@ -127,7 +127,7 @@ def test_naux5000_sampled_pi_and_properties(lib):
             assert np.all(w_im <= 1e-15)
             assert np.all(w_im >= -norm2[:, :, None] * (1 + 1e-9))
             assert np.all(np.diff(w_im, axis=2) >= -1e-13)
-    for key in ("f16x3", "f16x3r"):
+    for key in ("f16x3", "f16x3r", "f16r"):
         err = np.abs(qp[key] - qp["p64"]) / MEV
         print(key, "vs p64 (meV):", np.round(err, 4))
         assert np.max(err) <= 1.0

@@ -40,7 +40,10 @@ def run(lib, case, prec="p64", pade_tol=None, vxc=None, **kw):
 
 # --------------------------------------------------------------------- Pi
 
-@pytest.mark.parametrize("prec,tol", [("p64", 1e-12), ("b16x3", 3e-5), ("f16x3", 1e-6)])
+# one fp16 product: each product carries the operands' rounding, 2 * 2^-12
+# relative; near a resonance (z = x + 1e-3 i) a few terms dominate Pi and the
+# rounding does not average out, so the bar is 4 * 2^-12 of max|Pi|
+@pytest.mark.parametrize("prec,tol", [("p64", 1e-12), ("b16x3", 3e-5), ("f16x3", 1e-6), ("f16", 1e-3)])
 def test_polarizability_ragged(lib, prec, tol):
     case = cases.ragged()
     s = case.system
@@ -113,7 +116,8 @@ def test_sigma_and_qp_fp64(lib, which):
         assert g["sigma_x"] == pytest.approx(o.sigma_x[n], rel=1e-13)
 
 
-@pytest.mark.parametrize("prec,tol_mev,rank_tol", [("f16x3", 1.0, 0.0), ("f16x3", 1.0, 1e-10)])
+@pytest.mark.parametrize("prec,tol_mev,rank_tol", [("f16x3", 1.0, 0.0), ("f16x3", 1.0, 1e-10),
+                                                    ("f16", 1.0, 1e-10)])
 def test_qp_reduced_precision_within_1mev(lib, prec, tol_mev, rank_tol):
     for case in (cases.ragged(n_pade=32), cases.workload("fp64_1core_nmo60")):
         o = cases.oracle(case)
