@@ -40,21 +40,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(prec, workload):
+def measured_traffic(prec, workload, launches, planes):
     """HBM bytes per k_pi_gemm launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy), or None if
-    the summary is for another kernel source or configuration."""
+    the summary is for another kernel source, launch count or plane count."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_pi_gemm_{workload}_hbm_traffic.md")
     if prec != "f16" or not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "k_dense_sha256_16"):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "k_dense_sha256_16",
+                                                  "launches_per_step", "contracted_planes"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
     src = os.path.join(ROOT, "paper_2305_15955_amd", "csrc", "k_dense.hip")
     if vals.get("k_dense_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+        return None
+    if vals.get("launches_per_step") != str(launches) or vals.get("contracted_planes") != str(planes):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -162,6 +165,7 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / max(steps, 1)
         launches = lib.cdwac_get_timing_segments()
+        launches["planes"] = lib.cdwac_plane_counts()
         return out, dt, {k: v / max(steps, 1) for k, v in stage_sum.items()}, launches
 
     out, dt, stages, launches = run_steps(args.prec, use_mlp, args.warmup, args.steps)
@@ -179,12 +183,8 @@ def main():
     # roofline of the dominant kernel: the polarizability contraction, one
     # launch per batch of frequency planes; achieved = algorithmic flops of
     # one launch / its average duration (HIP events on the library's stream)
-    n_im_planes = len(freq)
-    if args.prec != "p64" and args.rank_tol > 0:
-        dmin = s.eps[s.n_occ] - s.eps[s.n_occ - 1]
-        dmax = s.eps[-1] - s.eps[0]
-        n_im_planes = len(cdwac.freq_decomposition(freq, dmin, dmax, args.rank_tol)[0])
-    n_f = n_im_planes + 2 * len(ref_re)          # planes the contraction computes
+    n_im_planes, n_f = launches["planes"]         # planes the contraction computes
+    res["config"]["imaginary_planes"] = n_im_planes
     res["config"]["contracted_planes"] = n_f
     k_dim = s.o_ia.shape[1]
     n_launch = max(int(launches["polarizability"]), 1)
@@ -200,7 +200,7 @@ def main():
     else:
         tile_elems = nb * (nb + 1) // 2 * 256 * 256        # lower-triangle 256 x 256 tiles
     issued = float(n_f) / n_launch * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
-    traffic = measured_traffic(args.prec, args.workload) if args.rank_tol == 1e-10 else None
+    traffic = measured_traffic(args.prec, args.workload, n_launch, n_f)
     res["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                        "frac": achieved / peak, "traffic": traffic,
                        "kernel": "k_pi_gemm" if args.prec != "p64" else "k_pi_f64",

@@ -106,12 +106,13 @@ typedef struct {
     int32_t prec;              /* cdwac_prec                                               */
     int32_t use_mlp_seed;      /* 1: start the root search at the learned seed             */
     double mlp_accept;         /* |f(seed)| (Ha) below which the seed is the answer        */
-    double freq_rank_tol;      /* 16-bit modes: > 0 computes Pi only at a skeleton of the
-                                  imaginary nodes and forms the others as combinations of
-                                  them (interpolative decomposition of the weights
-                                  c_f(D) = -2sD/(w_f^2 + D^2) over the transition-energy
-                                  range, sup-norm error <= tol relative to each c_f);
-                                  0 computes every node.  Ignored by CDWAC_P64.  [0, 1)   */
+    double freq_rank_tol;      /* 16-bit modes: > 0 runs Pi, the inversion and the W
+                                  contraction only at a skeleton of the imaginary nodes and
+                                  interpolates W^c_nm at the others (decomposition of the
+                                  family 1/(w^2 + Omega^2) over the RPA excitation range,
+                                  sup-norm error <= tol relative to each function's
+                                  maximum; falls back to every node if the range check
+                                  fails); 0 uses every node.  Ignored by CDWAC_P64.  [0, 1) */
 } cdwac_params;
 
 /* Result for one state (host, written by cdwac_qp / cdwac_solve). */
@@ -202,14 +203,20 @@ int cdwac_get_timing(const cdwac_ctx *ctx, double *ms, int32_t n);
  * ms[1] / count[1] is the average duration of one contraction launch. */
 int cdwac_get_timing_segments(const cdwac_ctx *ctx, int32_t *count, int32_t n);
 
+/* Planes of the last cdwac_prepare: imaginary nodes that went through Pi,
+ * the inversion and W (all n_freq, or the skeleton), and all planes
+ * (imaginary + 2 per near-real reference). */
+int cdwac_plane_counts(const cdwac_ctx *ctx, int32_t *n_imag, int32_t *n_planes);
+
 /* Host-only: the decomposition that freq_rank_tol selects.  For imaginary
- * nodes freq [n_freq] (> 0) and transition energies in [dmin, dmax] (Ha),
- * writes the skeleton node indices skel [*n_skel], the other indices rest
- * [n_freq - *n_skel] and T [n_freq - *n_skel][*n_skel] with
- * c_rest[r](D) ~= sum_s T[r][s] c_skel[s](D).  If no rank below n_freq meets
- * tol, *n_skel = n_freq and skel = 0 .. n_freq-1.  Output arrays must hold
- * n_freq (skel, rest) and n_freq^2 (T) entries.  tol in (0, 1). */
-int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double dmin, double dmax, double tol,
+ * nodes freq [n_freq] (> 0) and excitation energies in [omega_lo, omega_hi]
+ * (Ha), writes the skeleton node indices skel [*n_skel] (ascending, always
+ * including the largest node), the other indices rest [n_freq - *n_skel] and
+ * T [n_freq - *n_skel][*n_skel] with
+ * 1/(w_rest[r]^2 + O^2) ~= sum_s T[r][s] / (w_skel[s]^2 + O^2).  If no rank
+ * below n_freq meets tol, *n_skel = n_freq and skel = 0 .. n_freq-1.  Output
+ * arrays must hold n_freq (skel, rest) and n_freq^2 (T) entries.  tol in (0, 1). */
+int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double omega_lo, double omega_hi, double tol,
                              int32_t *n_skel, int32_t *skel, int32_t *rest, double *T);
 
 /* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------

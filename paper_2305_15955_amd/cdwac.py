@@ -87,6 +87,7 @@ _SIGNATURES = {
                                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                                  _f64p]),
+    "cdwac_plane_counts": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "cdwac_get_timing_segments": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "cdwac_mlp_set_model": (ctypes.c_int, [_vp, _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_float]),
     "cdwac_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
@@ -116,9 +117,10 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-def freq_decomposition(freq, dmin: float, dmax: float, tol: float):
-    """Host-only decomposition of the imaginary-axis weights (cdwac_freq_decomposition):
-    returns (skel, rest, T) with c_rest[r] ~= sum_s T[r, s] c_skel[s]."""
+def freq_decomposition(freq, omega_lo: float, omega_hi: float, tol: float):
+    """Host-only skeleton of the imaginary nodes (cdwac_freq_decomposition):
+    returns (skel, rest, T) with 1/(w_rest[r]^2 + O^2) ~= sum_s T[r, s] / (w_skel[s]^2 + O^2)
+    for O in [omega_lo, omega_hi]."""
     lib = load_library()
     w = np.ascontiguousarray(freq, np.float64)
     n = len(w)
@@ -126,7 +128,7 @@ def freq_decomposition(freq, dmin: float, dmax: float, tol: float):
     skel = np.zeros(n, np.int32)
     rest = np.zeros(n, np.int32)
     T = np.zeros(n * n, np.float64)
-    rc = lib.cdwac_freq_decomposition(n, _np_ptr(w, ctypes.c_double), float(dmin), float(dmax), float(tol),
+    rc = lib.cdwac_freq_decomposition(n, _np_ptr(w, ctypes.c_double), float(omega_lo), float(omega_hi), float(tol),
                                       ctypes.byref(ns), _np_ptr(skel, ctypes.c_int32),
                                       _np_ptr(rest, ctypes.c_int32), _np_ptr(T, ctypes.c_double))
     if rc != 0:
@@ -351,6 +353,11 @@ class Cdwac:
         ms = np.zeros(len(self.STAGES))
         _check(self.ctx, self.lib.cdwac_get_timing(self.ctx, _np_ptr(ms, ctypes.c_double), len(ms)))
         return dict(zip(self.STAGES, ms.tolist()))
+
+    def cdwac_plane_counts(self):
+        a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self.ctx, self.lib.cdwac_plane_counts(self.ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def cdwac_get_timing_segments(self):
         n = np.zeros(len(self.STAGES), np.int32)

@@ -35,7 +35,7 @@ struct Plan {
     // sizes
     int n_mo, n_occ, n_virt, n_aux, S, n_freq, n_im, n_re, n_pts, n_f, prec;
     int npad, cpad, cfpad, ni, n_fit, nblk, nb, n_tpi, n_tw, n_twf;
-    int n_comp;   // planes computed by the contraction (all, or skeleton + near-real)
+    int n_imp;    // imaginary-axis planes (every node, or the skeleton nodes)
     int64_t K, kpad;
     // persistent regions
     Region eps, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
@@ -43,7 +43,7 @@ struct Plan {
     // transient regions (prepare only)
     Region zr, zi, part, idflag, amax, sf, cw, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
         bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w, x32, yh, yl, t_pi, t_w,
-        t_wf, pmap, skel, rest, tmat;
+        t_wf, pmap, imnode, imrest, tmat, rowsum;
     size_t total = 0;
 };
 
@@ -61,6 +61,11 @@ struct HostState {
     int qp_maxit = 100, use_mlp = 0;
     double mlp_accept = 0.0;
     bool vxc_is_sigx = false;
+    // imaginary nodes with a plane (ascending), the others, and the
+    // interpolation of W at the others: W_rest[r] = sum_j T[r][j] W_node[j]
+    std::vector<int> node, rest;
+    std::vector<double> T;
+    double omega_lo = 0.0, omega_hi = 0.0;   // excitation range the decomposition assumes
 };
 
 }  // namespace
@@ -195,30 +200,31 @@ void fit_range(const double* eps, int n_mo, int n_occ, double lo, double hi, int
     m1 = n_occ + (int)(std::upper_bound(eps + n_occ, eps + n_mo, hi) - (eps + n_occ));
 }
 
-// ---- frequency decomposition of the imaginary-axis polarizabilities -------
-// On the imaginary axis Pi(i w_f) = X diag(c_f) X^T with
-// c_f(D) = -2 s D / (w_f^2 + D^2), a smooth family of functions of the
-// transition energy D in [dmin, dmax].  A row interpolative decomposition of
-// that family, c_f ~= sum_{s in S} T[f][s] c_s, gives
-// Pi(i w_f) ~= sum_s T[f][s] Pi(i w_s), so only the skeleton planes S need the
-// rank-K contraction.  The decomposition is taken on a logarithmic grid of
-// D (the weights vary on the scale of D itself) by column-pivoted
-// Gram-Schmidt with re-orthogonalisation; the rank is the smallest for which
-// the sup-norm error of every interpolated function on the grid is at most
-// tol times that function's maximum.  Returns false if no rank below n meets
-// tol (then every plane is computed).
+// ---- frequency decomposition of W on the imaginary axis -------------------
+// With the RPA excitation energies Omega_s and weights w_s >= 0 (Woodbury
+// form of Eq. bigLambda), W^c_nm(i w) = -sum_s w_s / (w^2 + Omega_s^2): every
+// W^c_nm lies in the span of the family h_w(Omega) = 1 / (w^2 + Omega^2),
+// Omega in [Omega_lo, Omega_hi].  A row interpolative decomposition
+// h_f ~= sum_j T[f][j] h_{node j} of that family therefore interpolates every
+// W^c_nm(i w_f) from its values at the skeleton nodes, which are the only
+// nodes that need Pi, the inversion and the W contraction.  The decomposition
+// is taken on a logarithmic grid of Omega by column-pivoted Gram-Schmidt with
+// re-orthogonalisation, starting from the largest node (whose plane the caller
+// uses to check Omega_hi); the rank is the smallest for which every
+// interpolated function is reproduced on the grid to tol times its maximum.
+// Returns false if no rank below n meets tol.
 struct FreqId {
-    std::vector<int> skel, rest;
-    std::vector<double> T;   // [rest.size()][skel.size()], for the unscaled weights
+    std::vector<int> skel, rest;   // skeleton ascending
+    std::vector<double> T;         // [rest.size()][skel.size()], columns in skel order
 };
 
-bool freq_id(const double* w, int n, double dmin, double dmax, double tol, FreqId& out) {
+bool freq_id(const double* w, int n, double lo, double hi, double tol, FreqId& out) {
     const int m = 2048;
     std::vector<double> G((size_t)m * n), A, scale(n, 0.0);
     for (int f = 0; f < n; ++f) {
         for (int j = 0; j < m; ++j) {
-            const double d = dmin * std::pow(dmax / dmin, (double)j / (m - 1));
-            const double g = d / (w[f] * w[f] + d * d);
+            const double om = lo * std::pow(hi / lo, (double)j / (m - 1));
+            const double g = 1.0 / (w[f] * w[f] + om * om);
             G[(size_t)f * m + j] = g;
             scale[f] = std::max(scale[f], g);
         }
@@ -229,6 +235,7 @@ bool freq_id(const double* w, int n, double dmin, double dmax, double tol, FreqI
     for (int i = 0; i < n; ++i) piv[i] = i;
     std::vector<double> R((size_t)n * n, 0.0);   // R[k * n + i], columns in pivot order
     auto col = [&](int c) { return &A[(size_t)c * m]; };
+    const int fmax = (int)(std::max_element(w, w + n) - w);
     int steps = 0;
     for (int k = 0; k < n; ++k) {
         int best = -1;
@@ -237,11 +244,11 @@ bool freq_id(const double* w, int n, double dmin, double dmax, double tol, FreqI
             const double* a = col(piv[i]);
             double s2 = 0.0;
             for (int j = 0; j < m; ++j) s2 += a[j] * a[j];
+            if (k == 0 && piv[i] == fmax) { best = i; bn = s2; break; }
             if (s2 > bn) { bn = s2; best = i; }
         }
         if (best < 0 || !(bn > 1e-300)) break;
         std::swap(piv[k], piv[best]);
-        // R columns already computed for rows < k follow the swap
         for (int r = 0; r < k; ++r) std::swap(R[(size_t)r * n + k], R[(size_t)r * n + best]);
         double* q = col(piv[k]);
         const double nq = std::sqrt(bn);
@@ -260,7 +267,6 @@ bool freq_id(const double* w, int n, double dmin, double dmax, double tol, FreqI
         }
         steps = k + 1;
     }
-    // smallest rank k whose interpolation error meets tol on the grid
     for (int k = 1; k < steps; ++k) {
         const int nr = n - k;
         std::vector<double> T((size_t)nr * k);
@@ -280,19 +286,32 @@ bool freq_id(const double* w, int n, double dmin, double dmax, double tol, FreqI
             }
         }
         if (worst <= tol) {
-            out.skel.assign(piv.begin(), piv.begin() + k);
+            // skeleton in ascending node order; T columns follow it
+            std::vector<int> order(k);
+            for (int c = 0; c < k; ++c) order[c] = c;
+            std::sort(order.begin(), order.end(), [&](int a, int b) { return piv[a] < piv[b]; });
+            out.skel.resize(k);
+            for (int c = 0; c < k; ++c) out.skel[c] = piv[order[c]];
             out.rest.assign(piv.begin() + k, piv.end());
             out.T.assign((size_t)nr * k, 0.0);
             for (int r = 0; r < nr; ++r)
                 for (int c = 0; c < k; ++c)
-                    out.T[(size_t)r * k + c] = T[(size_t)r * k + c] * scale[out.rest[r]] / scale[out.skel[c]];
+                    out.T[(size_t)r * k + c] =
+                        T[(size_t)r * k + order[c]] * scale[out.rest[r]] / scale[piv[order[c]]];
             return true;
         }
     }
     return false;
 }
 
-Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
+// Assumed bound of the RPA excitation energies for the decomposition: the
+// lowest is >= the lowest transition energy (Omega^2 = eig(D^2 + positive
+// semidefinite)); the highest is taken as 4 times the highest transition
+// energy and checked after Pi is known (cdwac_prepare falls back to every
+// node if the check fails).
+constexpr double kOmegaHiFactor = 4.0;
+
+Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool allow_id = true) {
     Plan P{};
     P.n_mo = s->n_mo;
     P.n_occ = s->n_occ;
@@ -303,9 +322,25 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     P.n_im = p->n_ref_im;
     P.n_re = p->n_ref_re;
     P.n_pts = P.n_im + P.n_re;
-    P.n_f = P.n_freq + 2 * P.n_re;
-    P.n_comp = P.n_f;
     P.prec = p->prec;
+    // imaginary nodes with a plane
+    std::vector<int> node, rest;
+    std::vector<double> T;
+    double om_lo = 0.0, om_hi = 0.0;
+    if (allow_id && P.prec != CDWAC_P64 && p->freq_rank_tol > 0.0 && P.n_freq >= 4) {
+        om_lo = s->eps[s->n_occ] - s->eps[s->n_occ - 1];
+        om_hi = kOmegaHiFactor * (s->eps[s->n_mo - 1] - s->eps[0]);
+        FreqId fid;
+        if (freq_id(p->freq, P.n_freq, om_lo, om_hi, p->freq_rank_tol, fid)) {
+            node = fid.skel;
+            rest = fid.rest;
+            T = fid.T;
+        }
+    }
+    if (node.empty())
+        for (int f = 0; f < P.n_freq; ++f) node.push_back(f);
+    P.n_imp = (int)node.size();
+    P.n_f = P.n_imp + 2 * P.n_re;
     P.K = (int64_t)P.n_occ * P.n_virt;
     P.kpad = round_up(P.K, 32);
     P.npad = (int)round_up(P.n_aux, kGemmRows);
@@ -325,6 +360,11 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     P.n_fit = (int)fs.size();
     P.cfpad = (int)round_up(std::max(P.n_fit, 1), kGemmCols);
     if (hs) {
+        hs->node = node;
+        hs->rest = rest;
+        hs->T = T;
+        hs->omega_lo = om_lo;
+        hs->omega_hi = om_hi;
         hs->m0 = m0;
         hs->m1 = m1;
         hs->fit_off = off;
@@ -363,9 +403,10 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
     add(P, P.part, sizeof(int) * P.n_f);
     add(P, P.idflag, sizeof(int) * P.n_f);
     add(P, P.pmap, sizeof(int) * P.n_f);
-    add(P, P.skel, sizeof(int) * P.n_freq);
-    add(P, P.rest, sizeof(int) * P.n_freq);
+    add(P, P.imnode, sizeof(int) * P.n_freq);
+    add(P, P.imrest, sizeof(int) * P.n_freq);
     add(P, P.tmat, sizeof(double) * (size_t)P.n_freq * P.n_freq);
+    add(P, P.rowsum, sizeof(double) * P.npad);
     // operand maxima: [0] |O^ia|, [1] |O^nm|, [2..2+F) |c_f|, [2+F..2+2F) |Lambda_f|
     add(P, P.amax, sizeof(uint32_t) * (2 + 2 * (size_t)P.n_f));
     // scales: [0] x, [1] B, cfac[F], pi_unscale[F], lam_scale[F], w_unscale[F]
@@ -392,9 +433,9 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
         add(P, P.t_wf, sizeof(int2) * P.n_twf);
     }
     add(P, P.E, sizeof(double) * (size_t)P.n_f * n2);
-    add(P, P.dinv_r, sizeof(double) * (size_t)std::max(P.n_freq, 1) * blk);
-    add(P, P.pbuf_r, sizeof(double) * (size_t)P.n_freq * P.nblk * blk);
-    add(P, P.qbuf_r, sizeof(double) * (size_t)P.n_freq * P.nblk * blk);
+    add(P, P.dinv_r, sizeof(double) * (size_t)std::max(P.n_imp, 1) * blk);
+    add(P, P.pbuf_r, sizeof(double) * (size_t)P.n_imp * P.nblk * blk);
+    add(P, P.qbuf_r, sizeof(double) * (size_t)P.n_imp * P.nblk * blk);
     add(P, P.dinv_c, sizeof(double) * 2 * (size_t)std::max(P.n_re, 1) * blk);
     add(P, P.pbuf_c, sizeof(double) * 2 * (size_t)P.n_re * P.nblk * blk);
     add(P, P.qbuf_c, sizeof(double) * 2 * (size_t)P.n_re * P.nblk * blk);
@@ -410,7 +451,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs) {
         add(P, P.bfh, sizeof(uint16_t) * (size_t)P.cfpad * P.npad);
         add(P, P.bfl, sizeof(uint16_t) * (size_t)P.cfpad * P.npad);
     }
-    add(P, P.partial_im, sizeof(double) * (size_t)P.n_freq * P.ni * P.cpad);
+    add(P, P.partial_im, sizeof(double) * (size_t)P.n_imp * P.ni * P.cpad);
     add(P, P.partial_re, sizeof(double) * 2 * (size_t)std::max(P.n_re, 1) * P.ni * P.cfpad);
     add(P, P.rowsel, sizeof(int) * std::max(P.n_fit, 1));
     add(P, P.ref_u, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * P.n_pts);
@@ -589,15 +630,25 @@ int cdwac_set_workspace(cdwac_ctx* ctx, void* dev_ptr, size_t bytes) {
     return CDWAC_OK;
 }
 
+namespace {
+int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, bool allow_id);
+}
+
 int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm) {
     if (!ctx) return CDWAC_EINVAL;
     ctx->prepared = false;
     TRY(validate_system(ctx, sys));
     TRY(validate_params(ctx, sys, prm));
     if (prm->use_mlp_seed && !ctx->have_mlp) return fail(ctx, CDWAC_EINVAL, "use_mlp_seed set but no model installed");
+    return prepare_impl(ctx, sys, prm, true);
+}
+
+namespace {
+int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, bool allow_id) {
     HIPCK(hipSetDevice(ctx->device));
     HostState hs;
-    Plan P = make_plan(sys, prm, &hs);
+    Plan P = make_plan(sys, prm, &hs, allow_id);
+    const bool use_id = !hs.rest.empty();
     TRY(ensure_workspace(ctx, P.total));
     ctx->plan = P;
     hipStream_t st = ctx->stream;
@@ -621,15 +672,15 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     // weight vectors: imaginary nodes, then (Re, Im) of every near-real point
     std::vector<double> zr(P.n_f), zi(P.n_f);
     std::vector<int> part(P.n_f), idf(P.n_f);
-    for (int k = 0; k < P.n_freq; ++k) {
+    for (int k = 0; k < P.n_imp; ++k) {
         zr[k] = 0.0;
-        zi[k] = prm->freq[k];
+        zi[k] = prm->freq[hs.node[k]];
         part[k] = 0;
         idf[k] = 1;
     }
     for (int j = 0; j < P.n_re; ++j)
         for (int q = 0; q < 2; ++q) {
-            int f = P.n_freq + 2 * j + q;
+            int f = P.n_imp + 2 * j + q;
             zr[f] = prm->ref_re[j];
             zi[f] = prm->eta_ref;
             part[f] = q;
@@ -658,30 +709,14 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     TRY(upload(ctx, at<double>(ctx, P.zi), zi.data(), P.n_f));
     TRY(upload(ctx, at<int>(ctx, P.part), part.data(), P.n_f));
     TRY(upload(ctx, at<int>(ctx, P.idflag), idf.data(), P.n_f));
-    // planes computed by the contraction: every plane, or the skeleton of the
-    // imaginary nodes plus the near-real planes (16-bit modes only)
-    FreqId fid;
-    bool use_id = false;
-    if (P.prec != CDWAC_P64 && prm->freq_rank_tol > 0.0 && P.n_freq >= 4) {
-        const double dmin = sys->eps[P.n_occ] - sys->eps[P.n_occ - 1];
-        const double dmax = sys->eps[P.n_mo - 1] - sys->eps[0];
-        use_id = freq_id(prm->freq, P.n_freq, dmin, dmax, prm->freq_rank_tol, fid);
-    }
-    std::vector<int> pmap;
-    if (use_id) {
-        pmap = fid.skel;
-        std::sort(pmap.begin(), pmap.end());
-    } else {
-        for (int f = 0; f < P.n_freq; ++f) pmap.push_back(f);
-    }
-    for (int f = P.n_freq; f < P.n_f; ++f) pmap.push_back(f);
-    P.n_comp = (int)pmap.size();
-    ctx->plan.n_comp = P.n_comp;
+    std::vector<int> pmap(P.n_f);
+    for (int f = 0; f < P.n_f; ++f) pmap[f] = f;
     TRY(upload(ctx, at<int>(ctx, P.pmap), pmap.data(), pmap.size()));
+    TRY(upload(ctx, at<int>(ctx, P.imnode), hs.node.data(), hs.node.size()));
     if (use_id) {
-        TRY(upload(ctx, at<int>(ctx, P.skel), fid.skel.data(), fid.skel.size()));
-        TRY(upload(ctx, at<int>(ctx, P.rest), fid.rest.data(), fid.rest.size()));
-        TRY(upload(ctx, at<double>(ctx, P.tmat), fid.T.data(), fid.T.size()));
+        TRY(upload(ctx, at<int>(ctx, P.imrest), hs.rest.data(), hs.rest.size()));
+        TRY(upload(ctx, at<double>(ctx, P.tmat), hs.T.data(), hs.T.size()));
+        HIPCK(hipMemsetAsync(at<double>(ctx, P.rowsum), 0, sizeof(double) * P.npad, st));
     }
     int* err = at<int>(ctx, P.err);
     HIPCK(hipMemsetAsync(err, 0, sizeof(int) * 4, st));
@@ -728,8 +763,8 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
         TRY(seg_end(ctx));
     } else {
         const int* pm = at<int>(ctx, P.pmap);
-        for (int f0 = 0; f0 < P.n_comp; f0 += P.nb) {
-            const int nfb = std::min(P.nb, P.n_comp - f0);
+        for (int f0 = 0; f0 < P.n_f; f0 += P.nb) {
+            const int nfb = std::min(P.nb, P.n_f - f0);
             TRY(seg_begin(ctx, 7));
             launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, pm + f0, nfb,
                             at<uint16_t>(ctx, P.yh), pi_split ? at<uint16_t>(ctx, P.yl) : nullptr);
@@ -743,17 +778,19 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
             LAUNCHCK();
             TRY(seg_end(ctx));
         }
-        if (use_id) {
-            TRY(seg_begin(ctx, 7));
-            launch_combine_planes(st, at<double>(ctx, P.E), P.npad, (int)fid.skel.size(), at<int>(ctx, P.skel),
-                                  (int)fid.rest.size(), at<int>(ctx, P.rest), at<double>(ctx, P.tmat));
-            LAUNCHCK();
-            TRY(seg_end(ctx));
-        }
+    }
+    if (use_id) {
+        // Gershgorin bound of -Pi at the largest node (always a skeleton node),
+        // for the check of the assumed excitation range
+        const int fslot = (int)(std::max_element(hs.node.begin(), hs.node.end(),
+                                                 [&](int a, int b) { return prm->freq[a] < prm->freq[b]; }) -
+                                hs.node.begin());
+        launch_rowabs(st, at<double>(ctx, P.E) + (int64_t)fslot * n2, P.npad, at<double>(ctx, P.rowsum));
+        LAUNCHCK();
     }
     // (a2) eps^-1 by blocked sweeps, Lambda = eps^-1 - I
     TRY(seg_begin(ctx, 2));
-    launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_freq, P.n_re, P.n_freq, at<double>(ctx, P.dinv_r),
+    launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_imp, P.n_re, P.n_imp, at<double>(ctx, P.dinv_r),
                  at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
                  at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
     LAUNCHCK();
@@ -782,13 +819,13 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
                            f64 ? nullptr : at<uint16_t>(ctx, P.bfl), P.cfpad, P.npad, nullptr, err);
         LAUNCHCK();
     }
-    launch_w(st, P.prec, P.npad, 0, P.n_freq, at<double>(ctx, P.E), f64 ? nullptr : at<uint16_t>(ctx, P.lh),
+    launch_w(st, P.prec, P.npad, 0, P.n_imp, at<double>(ctx, P.E), f64 ? nullptr : at<uint16_t>(ctx, P.lh),
              f64 ? nullptr : at<uint16_t>(ctx, P.ll), at<double>(ctx, P.bt64), f64 ? nullptr : at<uint16_t>(ctx, P.bh),
              f64 ? nullptr : at<uint16_t>(ctx, P.bl), P.cpad, f64 ? nullptr : at<int2>(ctx, P.t_w), P.n_tw, w_unscale,
              at<double>(ctx, P.partial_im));
     LAUNCHCK();
     if (P.n_re > 0 && P.n_fit > 0) {
-        launch_w(st, P.prec, P.npad, P.n_freq, 2 * P.n_re, at<double>(ctx, P.E),
+        launch_w(st, P.prec, P.npad, P.n_imp, 2 * P.n_re, at<double>(ctx, P.E),
                  f64 ? nullptr : at<uint16_t>(ctx, P.lh), f64 ? nullptr : at<uint16_t>(ctx, P.ll),
                  at<double>(ctx, P.bf64), f64 ? nullptr : at<uint16_t>(ctx, P.bfh),
                  f64 ? nullptr : at<uint16_t>(ctx, P.bfl), P.cfpad, f64 ? nullptr : at<int2>(ctx, P.t_wf), P.n_twf,
@@ -796,9 +833,14 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
         LAUNCHCK();
     }
     launch_reduce_w(st, at<double>(ctx, P.partial_im), at<double>(ctx, P.partial_re), P.ni, P.cpad, P.cfpad,
-                    P.n_freq, P.n_re, P.S * P.n_mo, P.n_re > 0 ? P.n_fit : 0, at<double>(ctx, P.w_im),
-                    at<double>(ctx, P.w_re));
+                    P.n_imp, at<int>(ctx, P.imnode), P.n_freq, P.n_re, P.S * P.n_mo, P.n_re > 0 ? P.n_fit : 0,
+                    at<double>(ctx, P.w_im), at<double>(ctx, P.w_re));
     LAUNCHCK();
+    if (use_id) {
+        launch_interp_w(st, at<double>(ctx, P.w_im), P.n_freq, P.S * P.n_mo, P.n_imp, at<int>(ctx, P.imnode),
+                        (int)hs.rest.size(), at<int>(ctx, P.imrest), at<double>(ctx, P.tmat));
+        LAUNCHCK();
+    }
     TRY(seg_end(ctx));
     // (a4) Sigma^x and v^xc
     TRY(seg_begin(ctx, 5));
@@ -821,13 +863,26 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
     TRY(seg_end(ctx));
     int herr[4] = {0, 0, 0, 0};
     HIPCK(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
+    std::vector<double> rows(use_id ? P.npad : 0);
+    if (use_id) HIPCK(hipMemcpyAsync(rows.data(), at<double>(ctx, P.rowsum), sizeof(double) * P.npad,
+                                     hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     TRY(seg_collect(ctx));
     if (herr[0] & 2) return fail(ctx, CDWAC_EINVAL, "non-finite value in the RI coefficients");
+    if (use_id) {
+        // Omega_max^2 <= D_max^2 + lambda_max(A A^T) and A A^T <= (w_max^2 + D_max^2) (-Pi(i w_max)),
+        // lambda_max(-Pi) <= its largest absolute row sum
+        const double g = *std::max_element(rows.begin(), rows.end());
+        const double dmax = sys->eps[P.n_mo - 1] - sys->eps[0];
+        const double wmax = *std::max_element(prm->freq, prm->freq + P.n_freq);
+        const double om_bound = std::sqrt(dmax * dmax + (wmax * wmax + dmax * dmax) * g);
+        if (!(om_bound <= hs.omega_hi)) return prepare_impl(ctx, sys, prm, false);
+    }
     if (herr[0] & 1) return fail(ctx, CDWAC_ENOTPD, "zero or non-finite pivot while inverting eps = I - Pi");
     ctx->hs = hs;
     ctx->prepared = true;
     return CDWAC_OK;
+}
 }
 
 int cdwac_qp(cdwac_ctx* ctx, const double* vxc, cdwac_state_out* out) {
@@ -1076,6 +1131,14 @@ int cdwac_freq_decomposition(int32_t n_freq, const double* freq, double dmin, do
     std::copy(fid.skel.begin(), fid.skel.end(), skel);
     std::copy(fid.rest.begin(), fid.rest.end(), rest);
     std::copy(fid.T.begin(), fid.T.end(), T);
+    return CDWAC_OK;
+}
+
+int cdwac_plane_counts(const cdwac_ctx* ctx, int32_t* n_imag, int32_t* n_planes) {
+    if (!ctx || !n_imag || !n_planes) return CDWAC_EINVAL;
+    if (!ctx->prepared) return CDWAC_ESTATE;
+    *n_imag = ctx->plan.n_imp;
+    *n_planes = ctx->plan.n_f;
     return CDWAC_OK;
 }
 

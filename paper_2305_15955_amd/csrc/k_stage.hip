@@ -329,14 +329,54 @@ __global__ void k_finalize_lambda(double* __restrict__ E, int npad, const int* _
 }
 
 // W_im[s][m][f] = sum_I partial[f][I][s*n_mo + m]
-__global__ void k_reduce_w_im(const double* __restrict__ partial, int ni, int cpad, int n_im, int ncols,
-                              double* __restrict__ w_im) {
+// W_im[c][node[f]] = sum_I partial[f][I][c] for the n_imp imaginary planes f
+// (row stride n_freq, the full grid).
+__global__ void k_reduce_w_im(const double* __restrict__ partial, int ni, int cpad, int n_imp,
+                              const int* __restrict__ node, int n_freq, int ncols, double* __restrict__ w_im) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= (int64_t)ncols * n_im) return;
-    int c = (int)(t / n_im), f = (int)(t % n_im);
+    if (t >= (int64_t)ncols * n_imp) return;
+    int c = (int)(t / n_imp), f = (int)(t % n_imp);
     double s = 0.0;
     for (int i = 0; i < ni; ++i) s += partial[((int64_t)f * ni + i) * cpad + c];
-    w_im[(int64_t)c * n_im + f] = s;
+    w_im[(int64_t)c * n_freq + node[f]] = s;
+}
+
+// W at the nodes without a plane: W_im[c][rest[r]] = sum_j T[r][j] W_im[c][node[j]].
+__global__ void k_interp_w_im(double* __restrict__ w_im, int n_freq, int ncols, int n_imp,
+                              const int* __restrict__ node, int n_rest, const int* __restrict__ rest,
+                              const double* __restrict__ T) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ncols * n_rest) return;
+    int c = (int)(t / n_rest), r = (int)(t % n_rest);
+    double* row = w_im + (int64_t)c * n_freq;
+    double s = 0.0;
+    for (int j = 0; j < n_imp; ++j) s += T[(int64_t)r * n_imp + j] * row[node[j]];
+    row[rest[r]] = s;
+}
+
+// Gershgorin bound of an imaginary-axis plane: rowsum[P] += sum_Q |E_PQ - delta_PQ|
+// over the symmetric matrix stored in the lower triangle; one 64 x 64 tile
+// per block, one row per wave at a time.
+__global__ void k_rowabs(const double* __restrict__ E, int npad, double* __restrict__ rowsum) {
+    __shared__ double cs[4][64];
+    int t = blockIdx.x, I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    const int q = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double csum = 0.0;
+    for (int p = wv; p < 64; p += 4) {
+        const int P = I * 64 + p, Q = J * 64 + q;
+        const double v = (I == J && Q > P) ? 0.0 : fabs(E[(int64_t)P * npad + Q] - (P == Q ? 1.0 : 0.0));
+        csum += v;
+        double r = v;
+        for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+        if (q == 0) atomicAdd(&rowsum[P], r);
+    }
+    cs[wv][q] = csum;
+    __syncthreads();
+    if (I != J && threadIdx.x < 64)
+        atomicAdd(&rowsum[J * 64 + threadIdx.x], cs[0][threadIdx.x] + cs[1][threadIdx.x] + cs[2][threadIdx.x] +
+                                                     cs[3][threadIdx.x]);
 }
 
 // W_re[fit][j] = (sum partial[2j], sum partial[2j+1]) of fit column.
@@ -368,41 +408,6 @@ __global__ void k_extract_pi(const double* __restrict__ E, int npad, int n, int 
     out[t] = -E[(int64_t)(2 * j + q) * npad * npad + (int64_t)a * npad + b];
 }
 
-
-// Planes that the frequency decomposition does not compute:
-//   E_f = sum_s T[r][s] E_{skel[s]} + (1 - sum_s T[r][s]) I,  f = rest[r],
-// which is eps_f = I - Pi_f with Pi_f = sum_s T[r][s] Pi_{skel[s]}.  Lower
-// triangle only; one block per 128 columns of one row.
-constexpr int kCombThreads = 128, kCombMax = 64;
-__global__ __launch_bounds__(kCombThreads) void k_combine_planes(double* __restrict__ E, int npad, int k,
-                                                                 const int* __restrict__ skel, int n_rest,
-                                                                 const int* __restrict__ rest,
-                                                                 const double* __restrict__ T) {
-    __shared__ double sv[kCombMax][kCombThreads];
-    __shared__ double st[kCombMax * kCombMax];
-    __shared__ double sd[kCombMax];
-    const int P = blockIdx.y, q0 = blockIdx.x * kCombThreads;
-    if (q0 > P) return;
-    const int t = threadIdx.x;
-    for (int i = t; i < n_rest * k; i += kCombThreads) st[i] = T[i];
-    __syncthreads();
-    if (t < n_rest) {
-        double a = 1.0;
-        for (int s = 0; s < k; ++s) a -= st[t * k + s];
-        sd[t] = a;
-    }
-    const int Q = q0 + t;
-    const bool ok = Q <= P;
-    const int64_t n2 = (int64_t)npad * npad, o = (int64_t)P * npad + Q;
-    for (int s = 0; s < k; ++s) sv[s][t] = ok ? E[(int64_t)skel[s] * n2 + o] : 0.0;
-    __syncthreads();
-    if (!ok) return;
-    for (int r = 0; r < n_rest; ++r) {
-        double a = P == Q ? sd[r] : 0.0;
-        for (int s = 0; s < k; ++s) a += st[r * k + s] * sv[s][t];
-        E[(int64_t)rest[r] * n2 + o] = a;
-    }
-}
 
 // ============================================================================
 // Host launchers
@@ -479,11 +484,17 @@ void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const i
     hipLaunchKernelGGL(k_finalize_lambda, dim3(T * n_f), dim3(256), 0, s, E, npad, idflag, lmax);
 }
 
-void launch_combine_planes(hipStream_t s, double* E, int npad, int k, const int* skel, int n_rest, const int* rest,
-                           const double* T) {
-    if (n_rest <= 0) return;
-    dim3 grid((unsigned)((npad + kCombThreads - 1) / kCombThreads), (unsigned)npad);
-    hipLaunchKernelGGL(k_combine_planes, grid, dim3(kCombThreads), 0, s, E, npad, k, skel, n_rest, rest, T);
+void launch_interp_w(hipStream_t s, double* w_im, int n_freq, int ncols, int n_imp, const int* node, int n_rest,
+                     const int* rest, const double* T) {
+    int64_t n = (int64_t)ncols * n_rest;
+    if (n > 0)
+        hipLaunchKernelGGL(k_interp_w_im, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w_im, n_freq, ncols,
+                           n_imp, node, n_rest, rest, T);
+}
+
+void launch_rowabs(hipStream_t s, const double* E, int npad, double* rowsum) {
+    const int nt = npad / 64;
+    hipLaunchKernelGGL(k_rowabs, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, E, npad, rowsum);
 }
 
 void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out) {
@@ -492,11 +503,12 @@ void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z,
 }
 
 void launch_reduce_w(hipStream_t s, const double* partial_im, const double* partial_re, int ni, int cpad, int cfpad,
-                     int n_im, int n_re, int ncols, int nfit, double* w_im, double* w_re) {
-    int64_t n1 = (int64_t)ncols * n_im;
+                     int n_imp, const int* node, int n_freq, int n_re, int ncols, int nfit, double* w_im,
+                     double* w_re) {
+    int64_t n1 = (int64_t)ncols * n_imp;
     if (n1 > 0)
         hipLaunchKernelGGL(k_reduce_w_im, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, s, partial_im, ni, cpad,
-                           n_im, ncols, w_im);
+                           n_imp, node, n_freq, ncols, w_im);
     int64_t n2 = (int64_t)nfit * n_re;
     if (n2 > 0)
         hipLaunchKernelGGL(k_reduce_w_re, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, partial_re, ni, cfpad,

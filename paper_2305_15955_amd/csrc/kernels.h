@@ -68,11 +68,15 @@ void launch_transpose_b(hipStream_t s, int et, const double* onm, int S, int N, 
                         int npad, uint32_t* bmax, int* err);
 void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, int n_occ, double* sx);
 void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax);
-void launch_combine_planes(hipStream_t s, double* E, int npad, int k, const int* skel, int n_rest, const int* rest,
-                           const double* T);
+// W at the imaginary nodes without a plane, from the nodes with one
+void launch_interp_w(hipStream_t s, double* w_im, int n_freq, int ncols, int n_imp, const int* node, int n_rest,
+                     const int* rest, const double* T);
+// rowsum[P] += sum_Q |E_PQ - delta_PQ| (lower-triangle storage; rowsum zeroed by the caller)
+void launch_rowabs(hipStream_t s, const double* E, int npad, double* rowsum);
 void launch_extract_pi(hipStream_t s, const double* E, int npad, int n, int n_z, int q, double* out);
 void launch_reduce_w(hipStream_t s, const double* partial_im, const double* partial_re, int ni, int cpad,
-                     int cfpad, int n_im, int n_re, int ncols, int nfit, double* w_im, double* w_re);
+                     int cfpad, int n_imp, const int* node, int n_freq, int n_re, int ncols, int nfit, double* w_im,
+                     double* w_re);
 
 // k_dense.hip
 constexpr int kGemmRows = 256;   // row block of the 16-bit contraction (A operand)

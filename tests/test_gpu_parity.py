@@ -13,6 +13,7 @@ import pytest
 
 import cases
 from oracle import cdwac_ref as R
+from paper_2305_15955_amd import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +28,11 @@ def lib():
     c = cdwac.Cdwac(0)
     yield c
     c.close()
+
+
+def cdwac_mod():
+    from paper_2305_15955_amd import cdwac
+    return cdwac
 
 
 def run(lib, case, prec="p64", pade_tol=None, vxc=None, **kw):
@@ -228,3 +234,38 @@ def test_error_paths(lib):
         run(fresh, nan, "b16x3")
     assert e.value.code == cdwac.CDWAC_EINVAL
     fresh.close()
+
+
+def test_skeleton_nodes_fall_back_when_excitations_exceed_the_range(lib):
+    """With very strong screening the RPA excitations exceed the range the
+    skeleton decomposition assumes; the range check after Pi then re-runs
+    with every node, so the result equals the run without decomposition."""
+    s = synth.make_system(60, 10, 200, 1, 0.9, kappa=0.2, seed=7)
+    case = cases.build(s, 32, 8, 8, (-320.0, -260.0), name="strong_screening")
+    outs = []
+    for rank_tol in (0.0, 1e-10):
+        run(lib, case, "f16x3", freq_rank_tol=rank_tol)
+        out = lib.cdwac_qp(1)
+        w_im, w_re, _, _ = lib.cdwac_w_table(1, s.n_mo, len(case.freq), len(case.ref_re))
+        outs.append((out[0], w_im, w_re))
+    (o0, wi0, wr0), (o1, wi1, wr1) = outs
+    np.testing.assert_array_equal(wi0, wi1)
+    np.testing.assert_array_equal(wr0, wr1)
+    assert o0["flags"] == o1["flags"]
+    assert (math.isnan(o0["qp"]) and math.isnan(o1["qp"])) or o0["qp"] == o1["qp"]
+
+
+def test_skeleton_nodes_interpolate_w(lib):
+    """Ragged case: W^c_nm at the nodes without a plane, interpolated from the
+    skeleton nodes, against the oracle's W at every node."""
+    case = cases.ragged()
+    o = cases.oracle(case)
+    run(lib, case, "f16x3", freq_rank_tol=1e-10)
+    s = case.system
+    w_im, _, _, _ = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+    dmin = s.eps[s.n_occ] - s.eps[s.n_occ - 1]
+    dmax = s.eps[-1] - s.eps[0]
+    skel, rest, T = cdwac_mod().freq_decomposition(case.freq, dmin, 4 * dmax, 1e-10)
+    assert 0 < len(rest) < len(case.freq)
+    err = np.max(np.abs(w_im - o.w_im)) / np.max(np.abs(o.w_im))
+    assert err < 1e-5, err

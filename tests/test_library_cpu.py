@@ -36,27 +36,35 @@ def test_params_layout_matches_header():
     assert ctypes.sizeof(cdwac.CdwacParams) == 8 + 16 + 8 + 8 + 8 + 8 + 3 * 8 + 2 * 8 + 8 + 3 * 4 + 4 + 2 * 8
 
 
-def test_freq_decomposition_interpolates_the_weights():
-    """Host logic of the imaginary-axis frequency decomposition: every
-    weight function c_f(D) = -2sD/(w_f^2 + D^2) is reproduced by the skeleton
-    nodes to the requested tolerance at transition energies off the grid."""
+def test_freq_decomposition_interpolates_w_family():
+    """Host logic of the imaginary-node skeleton: every 1/(w_f^2 + O^2) is
+    reproduced by the skeleton nodes to the requested tolerance (relative to its
+    maximum) at excitation energies off the decomposition's grid, and so is a
+    pole sum W(i w) = -sum_s p_s / (w^2 + O_s^2) with arbitrary p_s >= 0."""
     import numpy as np
     from paper_2305_15955_amd import grids
     w, _ = grids.gauss_legendre_imag(64)
-    dmin, dmax = 0.2, 13.0
+    lo, hi = 0.2, 50.0
     rng = np.random.default_rng(0)
-    d = np.sort(np.exp(rng.uniform(np.log(dmin), np.log(dmax), 20000)))
-    c = lambda f: -4.0 * d / (w[f] ** 2 + d ** 2)
+    om = np.sort(np.exp(rng.uniform(np.log(lo), np.log(hi), 20000)))
+    h = lambda f: 1.0 / (w[f] ** 2 + om ** 2)
     sizes = []
     for tol in (1e-6, 1e-10, 1e-13):
-        skel, rest, T = cdwac.freq_decomposition(w, dmin, dmax, tol)
+        skel, rest, T = cdwac.freq_decomposition(w, lo, hi, tol)
         assert len(set(skel) | set(rest)) == 64 and not set(skel) & set(rest)
+        assert 63 in skel and np.all(np.diff(skel) > 0)
         sizes.append(len(skel))
         for r, f in enumerate(rest):
-            approx = sum(T[r, j] * c(s) for j, s in enumerate(skel))
-            err = np.max(np.abs(approx - c(f))) / np.max(np.abs(c(f)))
-            assert err <= 3 * tol, (tol, f, err)
+            approx = sum(T[r, j] * h(s) for j, s in enumerate(skel))
+            assert np.max(np.abs(approx - h(f))) <= 3 * tol * np.max(h(f)), (tol, f)
+        # a pole sum with positive weights, as W^c_nm(i w) on the imaginary axis
+        poles = np.exp(rng.uniform(np.log(lo), np.log(hi), 40))
+        p = rng.uniform(0.0, 1.0, 40)
+        W = lambda f: -np.sum(p / (w[f] ** 2 + poles ** 2))
+        for r, f in enumerate(rest):
+            approx = sum(T[r, j] * W(s) for j, s in enumerate(skel))
+            assert abs(approx - W(f)) <= 3 * tol * np.sum(p) / (w[f] ** 2 + lo ** 2)
     assert sizes[0] < sizes[1] < sizes[2] < 64
     # a tolerance below what FP64 can certify keeps every node
-    skel, rest, T = cdwac.freq_decomposition(w, dmin, dmax, 1e-17)
+    skel, rest, T = cdwac.freq_decomposition(w, lo, hi, 1e-17)
     assert len(skel) == 64 and len(rest) == 0
