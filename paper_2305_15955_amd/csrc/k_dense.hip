@@ -183,8 +183,10 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 // one k-group reads 1 KiB of consecutive memory and lands in LDS through the
 // direct global-to-LDS path.  The waves form a 4 x 2 grid; each owns a 64 x 128
 // sub-tile (2 x 4 matrix-core blocks, 128 FP32 accumulators per lane).  K
-// advances in chunks of 32 through a 2-stage LDS ring of 64 KiB per stage:
-// chunk i+1 is in flight while chunk i is multiplied.  LDS layout per stage:
+// advances in chunks of 32 through an LDS ring of 128 KiB: 2 stages of 64 KiB
+// with the hi/lo split (chunk i+1 in flight while chunk i is multiplied), 4
+// stages of 32 KiB without it (three chunks in flight, since a chunk then
+// carries a third of the matrix-core work per byte).  LDS layout per stage:
 // [operand][plane][k-group of 8][row] x 16 bytes, so every fragment read is one
 // contiguous 16-byte word per lane and a half-wave reads 512 consecutive
 // bytes (no bank conflicts).  Products hi*hi + hi*lo + lo*hi accumulate in
@@ -193,10 +195,16 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 // and the workgroups an XCD runs together share operand panels in its L2.
 // ============================================================================
 
-constexpr int GT = 256, GK = 32, KGR = GK / 8, NST = 2;
+constexpr int GT = 256, GK = 32, KGR = GK / 8;
 constexpr int kGemmThreads = 512;
-constexpr int OP_STAGE = 2 * KGR * GT;          // uint4 slots of one operand per stage
-constexpr int STAGE = 2 * OP_STAGE;
+constexpr int kGemmLds = 8192;                  // uint4 slots of the LDS ring (128 KiB)
+// uint4 slots of one operand per stage, of a stage, and the ring depth
+template <bool SPLIT>
+struct Ring {
+    static constexpr int OP = (SPLIT ? 2 : 1) * KGR * GT;
+    static constexpr int STAGE = 2 * OP;
+    static constexpr int NST = kGemmLds / STAGE;
+};
 // 64-row-block loads per chunk: 2 operands x 2 planes x KGR k-groups x 4 row
 // blocks with the hi/lo split, the hi planes alone without it
 template <bool SPLIT>
@@ -227,16 +235,17 @@ __device__ inline void gemm_issue(uint4* lds, int st, const uint16_t* __restrict
         const int pl = SPLIT ? v >> 4 : 0, kg = (v >> 2) & 3, rb = v & 3;
         const uint16_t* base = op ? (pl ? bl : bh) : (pl ? al : ah);
         const uint16_t* g = base + (int64_t)rb * 64 * K + (k0 + kg * 8) * 64 + lane * 8;
-        const int slot = op * OP_STAGE + (pl * KGR + kg) * GT + rb * 64;
-        __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(lds + st * STAGE + slot), 16, 0, 0);
+        const int slot = op * Ring<SPLIT>::OP + (pl * KGR + kg) * GT + rb * 64;
+        __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(lds + st * Ring<SPLIT>::STAGE + slot), 16, 0,
+                                         0);
     }
 }
 
 template <int ET, bool SPLIT>
 __device__ inline void gemm_chunk(const uint4* lds, int st, int r0, int c0, int lane, v16f (&acc)[2][4]) {
     typedef typename Elem<ET>::vec V;
-    const uint4* sa = lds + st * STAGE;
-    const uint4* sb = sa + OP_STAGE;
+    const uint4* sa = lds + st * Ring<SPLIT>::STAGE;
+    const uint4* sb = sa + Ring<SPLIT>::OP;
     const int r = lane & 31, hg = lane >> 5;
 #pragma unroll
     for (int ks = 0; ks < GK / 16; ++ks) {
@@ -279,12 +288,18 @@ __device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, co
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v16f{};
-    gemm_issue<SPLIT>(lds, 0, ah, al, bh, bl, K, 0, w, lane);
+    constexpr int NST = Ring<SPLIT>::NST;
+    constexpr int ahead = (NST - 2) * loads_per_wave<SPLIT>();   // loads of later chunks left in flight
+#pragma unroll
+    for (int j = 0; j < NST - 1; ++j)
+        if (j < nk) gemm_issue<SPLIT>(lds, j, ah, al, bh, bl, K, j * GK, w, lane);
     for (int64_t i = 0; i < nk; ++i) {
         // chunk i has landed (own loads) and every wave is done with chunk i-1
-        __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+        if (i + NST - 2 < nk) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(ahead));
+        else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
         stage_barrier();
-        if (i + 1 < nk) gemm_issue<SPLIT>(lds, (int)((i + 1) % NST), ah, al, bh, bl, K, (i + 1) * GK, w, lane);
+        if (i + NST - 1 < nk)
+            gemm_issue<SPLIT>(lds, (int)((i + NST - 1) % NST), ah, al, bh, bl, K, (i + NST - 1) * GK, w, lane);
         gemm_chunk<ET, SPLIT>(lds, (int)(i % NST), r0, c0, lane, acc);
     }
 }
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
                                                           const double* __restrict__ pi_unscale,
                                                           const int* __restrict__ idflag, double* __restrict__ E,
                                                           int npad) {
-    __shared__ uint4 lds[NST * STAGE];
+    __shared__ uint4 lds[kGemmLds];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fb = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
@@ -343,7 +358,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
                                                          const int2* __restrict__ tiles, int n_tiles, int f0,
                                                          const double* __restrict__ w_unscale,
                                                          double* __restrict__ partial) {
-    __shared__ uint4 lds[NST * STAGE];
+    __shared__ uint4 lds[kGemmLds];
     __shared__ double red[4][GT];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fl = bid / n_tiles;
