@@ -196,6 +196,22 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
     const int lr = lane & 15, lk = lane >> 4;
     const int row = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 4;
+    // the tile of A is read before the product so that its loads overlap it
+    const int64_t n2 = (int64_t)npad * npad;
+    double *Er, *Ei;
+    mat_planes<C>(E, n2, mat, cbase, Er, Ei);
+    double er[2][2][4], ei[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t o = (int64_t)(I * kNb + wr * 32 + bi * 16 + lk + 4 * r) * npad + J * kNb + wc * 32 +
+                                  bj * 16 + lr;
+                er[bi][bj][r] = Er[o];
+                if (C) ei[bi][bj][r] = Ei[o];
+            }
     v4d ar[2][2] = {}, ai[2][2] = {};
     for (int k0 = 0; k0 < kNb; k0 += U_KC) {
 #pragma unroll
@@ -240,9 +256,6 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
         }
         __syncthreads();
     }
-    const int64_t n2 = (int64_t)npad * npad;
-    double *Er, *Ei;
-    mat_planes<C>(E, n2, mat, cbase, Er, Ei);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -252,8 +265,8 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
                 int P_ = I * kNb + wr * 32 + bi * 16 + lk + 4 * r;
                 int Q_ = J * kNb + wc * 32 + bj * 16 + lr;
                 int64_t o = (int64_t)P_ * npad + Q_;
-                Er[o] -= ar[bi][bj][r];
-                if (C) Ei[o] -= ai[bi][bj][r];
+                Er[o] = er[bi][bj][r] - ar[bi][bj][r];
+                if (C) Ei[o] = ei[bi][bj][r] - ai[bi][bj][r];
             }
 }
 
