@@ -208,6 +208,16 @@ def main():
                        "launch_ms": launch_s * 1e3,
                        "mfma_issued_frac": issued / launch_s / PEAK[args.prec]}
     res["stages_ms"] = stages
+    # spectral function (Sec. 4) on 5000 points per state over a 50 eV range,
+    # from the prepared tables of the last step
+    om = np.stack([s.eps[s.state_idx[n]] + np.linspace(-25.0, 25.0, 5000) / synth.HARTREE_EV
+                   for n in range(s.n_states)])
+    lib.cdwac_spectral(om)
+    torch.cuda.synchronize()
+    t_sp = time.perf_counter()
+    spec = lib.cdwac_spectral(om)
+    res["spectral_5000pts_ms"] = (time.perf_counter() - t_sp) * 1e3
+    res["spectral_peak_ev"] = [float(om[n, int(np.argmax(spec[n]))] * synth.HARTREE_EV) for n in range(s.n_states)]
     res["qp_ev"] = [o["qp"] * synth.HARTREE_EV for o in out]
     res["n_evals_mean"] = float(np.mean([o["n_evals"] for o in out]))
 

@@ -160,6 +160,16 @@ int cdwac_solve(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm
 int cdwac_sigma(cdwac_ctx *ctx, int32_t n_omega, const double *omega, double *sigma,
                 double *i_term, double *r_term);
 
+/* Diagonal spectral function (Sec. 4): with the complex self-energy
+ * Sigma_n = Sigma^x + R_n - I_n (the imaginary part comes from the residue
+ * term, i.e. from the Pade models at |eps_m - w| + i eta),
+ *   A_n(w) = (1/pi) |Im[1 / (w - eps_n - Sigma_n(w) + v^xc_n)]|.
+ * omega, spectral: device [n_states][n_omega] (Ha, 1/Ha); sigma_re, sigma_im:
+ * device, same shape, or NULL.  vxc: host [n_states] or NULL (the value in
+ * use; a non-NULL vxc replaces it, as in cdwac_qp).  n_omega <= 65535 per call. */
+int cdwac_spectral(cdwac_ctx *ctx, int32_t n_omega, const double *omega, const double *vxc, double *spectral,
+                   double *sigma_re, double *sigma_im);
+
 /* Copies of the prepared tables (device outputs):
  * w_im [n_states][n_mo][n_freq]  W^c_nm(i omega_k), real;
  * w_re [n_fit][n_ref_re][2]      W^c_nm(x_j + i eta_ref) for the fitted (n, m),

@@ -228,19 +228,33 @@ def integral_term(omega: float, eps: np.ndarray, w_imag: np.ndarray,
     return float(np.sum(weight[None, :] * w_imag * kern) / math.pi)
 
 
-def residue_term(omega: float, eps: np.ndarray, eps_f: float, eta: float,
-                 w_at: Callable[[int, complex], complex]) -> float:
-    """Re R_n(omega) of Eq. (Rn_term): sum_m f_m W^c_nm(|eps_m - omega| + i eta).
+def residue_term_complex(omega: float, eps: np.ndarray, eps_f: float, eta: float,
+                         w_at: Callable[[int, complex], complex]) -> complex:
+    """R_n(omega) of Eq. (Rn_term): sum_m f_m W^c_nm(|eps_m - omega| + i eta).
 
     ``w_at(m, z)`` returns W^c_nm(z) (a Pade model for CD-WAC, a direct
-    evaluation for full CD).
+    evaluation for full CD).  Its real part enters the QP equation; its
+    imaginary part is the imaginary part of Sigma_n (the integral term is real
+    with eta -> 0), which the spectral function needs.
     """
     f = occupation_factor(eps, eps_f, omega)
-    total = 0.0
+    total = 0j
     for m in np.nonzero(f)[0]:
         z = abs(float(eps[m]) - omega) + 1j * eta
-        total += f[m] * complex(w_at(int(m), z)).real
-    return float(total)
+        total += f[m] * complex(w_at(int(m), z))
+    return complex(total)
+
+
+def residue_term(omega: float, eps: np.ndarray, eps_f: float, eta: float,
+                 w_at: Callable[[int, complex], complex]) -> float:
+    """Re R_n(omega) of Eq. (Rn_term)."""
+    return float(residue_term_complex(omega, eps, eps_f, eta, w_at).real)
+
+
+def spectral_function(omega: float, eps_n: float, sigma: complex, vxc: float) -> float:
+    """A_nn(omega) = (1/pi) |Im[(omega - eps_n - Sigma_n(omega) + v^xc_n)^-1]|
+    (the diagonal spectral function of Sec. 4, normalised like a Lorentzian)."""
+    return abs((1.0 / (omega - eps_n - sigma + vxc)).imag) / math.pi
 
 
 def fit_range(eps: np.ndarray, n_occ: int, lo: float, hi: float):
@@ -403,6 +417,18 @@ class CdwacOracle:
 
     def sigma_c(self, s: int, omega: float) -> float:
         return self.sigma(s, omega) - self.sigma_x[s]
+
+    def sigma_complex(self, s: int, omega: float) -> complex:
+        """Sigma^x + R - I with the complex residue term."""
+        i_term = integral_term(omega, self.eps, self.w_im[s], self.freq, self.weight)
+        r_term = residue_term_complex(omega, self.eps, self.eps_f, self.eta,
+                                      lambda m, z: self.w_model(s, m, z))
+        return self.sigma_x[s] + r_term - i_term
+
+    def spectral(self, s: int, omega: float, vxc: Optional[float] = None) -> float:
+        n = int(self.sys.state_idx[s])
+        v = float(self.vxc[s]) if vxc is None else vxc
+        return spectral_function(omega, float(self.eps[n]), self.sigma_complex(s, omega), v)
 
     def solve(self, s: int, tol: float = 1e-10, maxit: int = 100):
         n = int(self.sys.state_idx[s])

@@ -87,6 +87,7 @@ _SIGNATURES = {
                                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                                  _f64p]),
+    "cdwac_spectral": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _f64p, _vp, _vp, _vp]),
     "cdwac_plane_counts": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "cdwac_get_timing_segments": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "cdwac_mlp_set_model": (ctypes.c_int, [_vp, _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_float]),
@@ -293,6 +294,21 @@ class Cdwac:
         if terms:
             return sig.cpu().numpy(), it.cpu().numpy(), rt.cpu().numpy()
         return sig.cpu().numpy()
+
+    def cdwac_spectral(self, omega, vxc=None, parts: bool = False):
+        """omega: [n_states, n_omega] (Ha) -> A_n(omega) (and Re, Im Sigma) as numpy."""
+        t = self.torch
+        om = self._dev(np.atleast_2d(omega))
+        spec = t.empty_like(om)
+        sre = t.empty_like(om) if parts else None
+        sim = t.empty_like(om) if parts else None
+        vx = None if vxc is None else np.ascontiguousarray(vxc, np.float64)
+        _check(self.ctx, self.lib.cdwac_spectral(self.ctx, om.shape[1], _ptr(om),
+                                                 None if vx is None else _np_ptr(vx, ctypes.c_double),
+                                                 _ptr(spec), _ptr(sre), _ptr(sim)))
+        if parts:
+            return spec.cpu().numpy(), sre.cpu().numpy(), sim.cpu().numpy()
+        return spec.cpu().numpy()
 
     def cdwac_fit_ranges(self, n_states: int):
         m0 = np.zeros(n_states, np.int32)

@@ -931,6 +931,24 @@ int cdwac_sigma(cdwac_ctx* ctx, int32_t n_omega, const double* omega, double* si
     return CDWAC_OK;
 }
 
+int cdwac_spectral(cdwac_ctx* ctx, int32_t n_omega, const double* omega, const double* vxc, double* spectral,
+                   double* sigma_re, double* sigma_im) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_spectral called before cdwac_prepare");
+    if (n_omega < 0 || (n_omega > 0 && (!omega || !spectral))) return fail(ctx, CDWAC_EINVAL, "bad omega/spectral");
+    if (n_omega > 65535) return fail(ctx, CDWAC_EINVAL, "n_omega must be <= 65535");
+    if (vxc)
+        for (int j = 0; j < ctx->plan.S; ++j)
+            if (!std::isfinite(vxc[j])) return fail(ctx, CDWAC_EINVAL, "vxc[%d] is not finite", j);
+    HIPCK(hipSetDevice(ctx->device));
+    if (vxc) TRY(upload(ctx, at<double>(ctx, ctx->plan.vxc), vxc, ctx->plan.S));
+    QpArgs a = qp_args(ctx);
+    launch_spectral(ctx->stream, a, n_omega, omega, spectral, sigma_re, sigma_im);
+    LAUNCHCK();
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return CDWAC_OK;
+}
+
 int cdwac_w_table(cdwac_ctx* ctx, double* w_im, double* w_re, double* sigma_x) {
     if (!ctx) return CDWAC_EINVAL;
     if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_w_table called before cdwac_prepare");

@@ -44,8 +44,9 @@ struct Shared {
     float h2[64];
 };
 
-// I_n(omega) and Re R_n(omega) for state s.
-__device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R) {
+// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).
+__device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R,
+                            double* Ri = nullptr) {
     const int nf = A.n_freq;
     const double* W = A.w_im + (int64_t)s * A.n_mo * nf;
     double isum = 0.0;
@@ -57,7 +58,7 @@ __device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, do
         for (int k = 0; k < nf; ++k) acc += sh.weight[k] * wm[k] * (am / (am2 + sh.freq[k] * sh.freq[k]));
         isum += acc;
     }
-    double rsum = 0.0;
+    double rsum = 0.0, risum = 0.0;
     const int m0 = A.m0[s], m1 = A.m1[s], foff = A.fit_off[s];
     for (int m = m0 + threadIdx.x; m < m1; m += kQpThreads) {
         double em = A.eps[m];
@@ -77,9 +78,11 @@ __device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, do
             val = cmk(a[0], a[1]) / t;
         }
         rsum += fm * val.re;
+        risum += fm * val.im;
     }
     I = block_sum(isum, sh.red) / kPi;
     R = block_sum(rsum, sh.red);
+    if (Ri) *Ri = block_sum(risum, sh.red);
 }
 
 __device__ inline double sigma_total(const QpArgs& A, int s, double omega, Shared& sh) {
@@ -277,7 +280,42 @@ __global__ __launch_bounds__(kQpThreads) void k_sigma_eval(QpArgs A, int n_omega
     }
 }
 
+// Diagonal spectral function (Sec. 4): with Sigma_n = Sigma^x + R_n - I_n
+// complex (Im from the residue term; the integral term is real for eta -> 0),
+// A_n(w) = (1/pi) |Im[1 / (w - eps_n - Sigma_n(w) + v^xc_n)]|.
+__global__ __launch_bounds__(kQpThreads) void k_spectral_eval(QpArgs A, int n_omega,
+                                                              const double* __restrict__ omega,
+                                                              double* __restrict__ spec,
+                                                              double* __restrict__ sre,
+                                                              double* __restrict__ sim) {
+    __shared__ Shared sh;
+    const int k = blockIdx.x, s = blockIdx.y;
+    for (int q = threadIdx.x; q < A.n_freq; q += kQpThreads) {
+        sh.freq[q] = A.freq[q];
+        sh.weight[q] = A.weight[q];
+    }
+    __syncthreads();
+    const int64_t o = (int64_t)s * n_omega + k;
+    const double w = omega[o];
+    double I, R, Ri;
+    sigma_terms(A, s, w, sh, I, R, &Ri);
+    if (threadIdx.x == 0) {
+        const double re = A.sigx[s] + R - I;
+        const double dr = w - A.eps[A.state_idx[s]] - re + A.vxc[s], di = -Ri;
+        spec[o] = fabs(di) / (dr * dr + di * di) / kPi;
+        if (sre) sre[o] = re;
+        if (sim) sim[o] = Ri;
+    }
+}
+
 int qp_max_freq() { return kMaxFreq; }
+
+void launch_spectral(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* spec, double* sre,
+                     double* sim) {
+    if (n_omega <= 0) return;
+    hipLaunchKernelGGL(k_spectral_eval, dim3(n_omega, a.n_states), dim3(kQpThreads), 0, s, a, n_omega, omega, spec,
+                       sre, sim);
+}
 
 void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out) {
     hipLaunchKernelGGL(k_qp_solve, dim3(a.n_states), dim3(kQpThreads), 0, s, a, out);

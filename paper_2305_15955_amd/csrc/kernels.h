@@ -111,6 +111,8 @@ int qp_max_freq();
 void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out);
 void launch_sigma(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* sigma,
                   double* iterm, double* rterm);
+void launch_spectral(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* spec, double* sre,
+                     double* sim);
 
 // k_mlp.hip
 constexpr int kMlpParams = 4801;

@@ -269,3 +269,57 @@ def test_skeleton_nodes_interpolate_w(lib):
     assert 0 < len(rest) < len(case.freq)
     err = np.max(np.abs(w_im - o.w_im)) / np.max(np.abs(o.w_im))
     assert err < 1e-5, err
+
+
+def sigma_sensitivity(case, o, oms, rel=1e-13, trials=2, seed=1):
+    """Largest relative change of the oracle's complex Sigma at each omega when
+    every W^c_nm table entry is perturbed by ~rel relative (the conditioning of
+    the continuation at that omega)."""
+    s = case.system
+    rng = np.random.default_rng(seed)
+    base = np.array([[o.sigma_complex(n, w) for w in oms[n]] for n in range(s.n_states)])
+    scale = np.abs(o.sigma_x)[:, None] + np.abs(base)
+    worst = np.zeros(oms.shape)
+    for _ in range(trials):
+        o2 = cases.oracle(case)
+        o2.w_im = o.w_im * (1 + rel * rng.standard_normal(o.w_im.shape))
+        o2.w_re = o.w_re * (1 + rel * rng.standard_normal(o.w_re.shape))
+        for n in range(s.n_states):
+            m0, m1 = R.fit_range(o2.eps, s.n_occ, o2.win_lo[n] - R.QP_Z_STEP, o2.win_hi[n] + R.QP_Z_STEP)
+            o2.fits[n] = {m: R.thiele_greedy(*o2.reference_data(n, m), o2.pade_tol) for m in range(m0, m1)}
+        pert = np.array([[o2.sigma_complex(n, w) for w in oms[n]] for n in range(s.n_states)])
+        worst = np.maximum(worst, np.abs(pert - base) / scale)
+    return base, scale, worst
+
+
+@pytest.mark.parametrize("which", ["ragged", "fp64_1core_nmo60", "one_transition"])
+def test_spectral_function_fp64(lib, which):
+    """Diagonal spectral function (Sec. 4) on a dense grid through the whole
+    window.  The complex self-energy agrees to 1e-9 of its scale or to 100
+    times the oracle's own change under a 1e-13 perturbation of W, whichever
+    is larger (far below eps_n the continuation amplifies last-digit
+    differences of W by up to ~1e7).  A_n agrees to the accuracy that follows:
+    A is proportional to |Im Sigma| / |D|^2 with D = w - eps - Sigma + vxc, so
+    |dA| / A <= |dSigma| (1 / |Im Sigma| + 2 / |D|)."""
+    case = {"ragged": cases.ragged, "one_transition": cases.one_transition}.get(
+        which, lambda: cases.workload(which))()
+    o = cases.oracle(case)
+    run(lib, case, "p64")
+    s = case.system
+    n_om = 41
+    oms = np.stack([np.linspace(case.lo[n], case.hi[n], n_om) for n in range(s.n_states)])
+    spec, sre, sim = lib.cdwac_spectral(oms, parts=True)
+    base, scale, sens = sigma_sensitivity(case, o, oms)
+    tol = np.maximum(1e-9, 100.0 * sens)
+    for n in range(s.n_states):
+        e_n = s.eps[s.state_idx[n]]
+        for k in range(n_om):
+            w, sig = oms[n, k], base[n, k]
+            ds = tol[n, k] * scale[n, k]
+            assert abs(sre[n, k] - sig.real) <= ds, (n, k, tol[n, k])
+            assert abs(sim[n, k] - sig.imag) <= ds, (n, k, tol[n, k])
+            a_ref = o.spectral(n, w)
+            d = abs(w - e_n - sig + o.vxc[n])
+            bound = a_ref * ds * (1.0 / max(abs(sig.imag), ds) + 2.0 / d)
+            assert abs(spec[n, k] - a_ref) <= bound + 1e-300, (n, k, spec[n, k], a_ref)
+    print(which, "largest tolerance", tol.max())

@@ -351,3 +351,27 @@ def test_qp_fallback_rejects_steep_pole_crossing():
     g = lambda x: (x - 0.33) * (x - x0) ** 2 / ((x - x0) ** 2 + 1e-6)
     qp, z, nev, flags = R.qp_solve(g, 0.3, 0.25, 0.35)
     assert abs(qp - 0.33) < 1e-10
+
+
+def test_complex_residue_term_matches_pole_form_for_one_transition():
+    """Sec. 4 spectral function: for a single transition W^c_nm(z) is exactly
+    c / (z^2 - Omega^2) (pole form), which the Pade model reproduces after two
+    terms; the complex residue term then equals sum_m f_m c_nm / ((|eps_m -
+    omega| + i eta)^2 - Omega^2) and its imaginary part is Im Sigma."""
+    import cases
+    case = cases.one_transition()
+    o = cases.oracle(case)
+    s = case.system
+    om, coup = R.rpa_poles(s)
+    for w in np.linspace(-12.0, -8.0, 23):
+        sig = o.sigma_complex(0, w)
+        i_term = R.integral_term(w, s.eps, o.w_im[0], case.freq, case.weight)
+        f = R.occupation_factor(s.eps, o.eps_f, w)
+        ref = sum(f[m] * R.w_poles(om, coup, abs(s.eps[m] - w) + 1j * case.eta)[0, m]
+                  for m in range(len(s.eps)) if f[m] != 0)
+        got = sig - o.sigma_x[0] + i_term
+        assert abs(got - ref) <= 1e-10 * max(abs(ref), abs(o.sigma_x[0]), abs(i_term)), w
+        assert sig.real == pytest.approx(o.sigma(0, w), rel=1e-13, abs=1e-15)
+        # the spectral function is the Lorentzian-normalised |Im G|
+        d = w - s.eps[0] - sig + o.vxc[0]
+        assert o.spectral(0, w) == pytest.approx(abs(sig.imag) / abs(d) ** 2 / math.pi, rel=1e-12)
