@@ -94,7 +94,9 @@ typedef struct {
     const double *weight;      /* host [n_freq]: quadrature weights for int_0^inf          */
     int32_t n_ref_im;          /* imaginary nodes re-used as Pade references               */
     const int32_t *ref_im_idx; /* host [n_ref_im]: distinct indices into freq              */
-    int32_t n_ref_re;          /* near-real Pade references x_j + i*eta_ref                */
+    int32_t n_ref_re;          /* near-real Pade references x_j + i*eta_ref;
+                                  1 <= n_ref_im + n_ref_re <= 256 (M of the paper's
+                                  CD-WAC(N_core, N_valence, N_Im) is at most 240)         */
     const double *ref_re;      /* host [n_ref_re]: x_j >= 0                                */
     double eta_ref;            /* imaginary part of the near-real references (> 0)         */
     double eta;                /* broadening of the residue term, W(|eps_m - w| + i eta)   */
@@ -190,7 +192,7 @@ int cdwac_polarizability(cdwac_ctx *ctx, const cdwac_system *sys, int32_t prec, 
  * their values at n_x points each.  u, w: device [n_fit][n_pts][2] (complex
  * u_j = z_j^2 and W_j); x: device [n_fit][n_x][2] (complex z^2 at which to
  * evaluate); out: device [n_fit][n_x][2]; n_terms: device [n_fit] or NULL.
- * n_pts <= 64. */
+ * n_pts <= 256. */
 int cdwac_pade_fit_eval(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const double *u,
                         const double *w, double tol, int32_t n_x, const double *x,
                         double *out, int32_t *n_terms);

@@ -21,8 +21,8 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 constexpr int kPad = 128;
 // Block size of the blocked symmetric sweep (Gauss-Jordan) inversion.
 constexpr int kNb = 64;
-// Largest number of Pade reference points (one wave lane per point).
-constexpr int kMaxPade = 64;
+// Largest number of Pade reference points (a fit wave holds 4 per lane).
+constexpr int kMaxPade = 256;
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -1,9 +1,10 @@
 // Greedy Thiele-Pade fits of W^c_nm (Sec. 2.4, Eqs. pade, pre_rec, rec_eq;
-// Sec. 3.2), FP64 complex.  One wave per fit, one lane per reference point
-// (at most 64).  Lane j keeps u_j = z_j^2, W_j and its current reciprocal
-// difference g(u_j); lane q also keeps the q-th chosen coefficient a_q and
-// node u_q, so evaluating the convergent at every remaining point is a loop
-// of lane broadcasts.
+// Sec. 3.2), FP64 complex.  One wave per fit; reference point j lives in lane
+// j % 64, slot j / 64 (up to 4 slots, so at most 256 points, enough for the
+// paper's default CD-WAC(20, 20, 200)).  Each point keeps u_j = z_j^2, W_j
+// and its current reciprocal difference g(u_j).  The chosen coefficients a_q
+// and nodes u_q go to the wave's LDS slice, from where every lane reads them
+// (broadcast) to evaluate the convergent at its remaining points.
 //
 // Order (greedy): the first point is the largest |W_j|; afterwards the point
 // where the current convergent has the largest L1 error |Re(W-T)| + |Im(W-T)|
@@ -17,7 +18,7 @@ namespace cdwac {
 
 __device__ inline double shfl_d(double v, int src) { return __shfl(v, src, 64); }
 
-// Wave arg-max with the lowest index on ties; returns the winning lane.
+// Wave arg-max with the lowest index on ties; returns the winning index.
 __device__ inline int wave_argmax(double v, int idx, double& best) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -32,69 +33,112 @@ __device__ inline int wave_argmax(double v, int idx, double& best) {
     return idx;
 }
 
-// Convergent with p terms held by lanes 0..p-1, evaluated at u (per lane).
-__device__ inline cplx eval_lanes(cplx u, double a_re, double a_im, double n_re, double n_im, int p) {
-    cplx t = cmk(1.0, 0.0);
-    for (int q = p - 1; q >= 1; --q) {
-        cplx aq = cmk(shfl_d(a_re, q), shfl_d(a_im, q));
-        cplx nq = cmk(shfl_d(n_re, q - 1), shfl_d(n_im, q - 1));
-        t = cmk(1.0, 0.0) + (aq * (u - nq)) / t;
-    }
-    cplx a0 = cmk(shfl_d(a_re, 0), shfl_d(a_im, 0));
-    return a0 / t;
+// Per-lane arg-max over the lane's slots (ascending index, so a strict '>'
+// keeps the lowest index), then across the wave.
+template <int P>
+__device__ inline int points_argmax(const double (&v)[P], int lane, double& best) {
+    double bv = v[0];
+    int bi = lane;
+#pragma unroll
+    for (int s = 1; s < P; ++s)
+        if (v[s] > bv) {
+            bv = v[s];
+            bi = lane + 64 * s;
+        }
+    return wave_argmax(bv, bi, best);
 }
 
+// Value of slot `slot` (wave-uniform) of lane `src`.
+template <int P>
+__device__ inline cplx pick(const cplx (&v)[P], int slot, int src) {
+    cplx x = v[0];
+#pragma unroll
+    for (int s = 1; s < P; ++s)
+        if (slot == s) x = v[s];
+    return cmk(shfl_d(x.re, src), shfl_d(x.im, src));
+}
+
+// Convergent with p terms (coefficients a[], nodes nd[] in LDS) at u.
+__device__ inline cplx eval_terms(cplx u, const cplx* a, const cplx* nd, int p) {
+    cplx t = cmk(1.0, 0.0);
+    for (int q = p - 1; q >= 1; --q) t = cmk(1.0, 0.0) + (a[q] * (u - nd[q - 1])) / t;
+    return a[0] / t;
+}
+
+template <int P>
 __global__ __launch_bounds__(256) void k_thiele_fit(int n_fit, int n_pts, const double* __restrict__ u,
                                                     const double* __restrict__ w, double tol,
                                                     double* __restrict__ coef, double* __restrict__ node,
                                                     int* __restrict__ nterm) {
-    const int fit = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ cplx s_a[4][64 * P];
+    __shared__ cplx s_n[4][64 * P];
+    const int wv = threadIdx.x >> 6;
+    const int fit = blockIdx.x * 4 + wv;
     const int lane = threadIdx.x & 63;
     if (fit >= n_fit) return;                       // whole wave leaves together
-    const bool valid = lane < n_pts;
-    const int64_t base = ((int64_t)fit * n_pts + (valid ? lane : 0)) * 2;
-    cplx uj = valid ? cmk(u[base], u[base + 1]) : cmk(0.0, 0.0);
-    cplx wj = valid ? cmk(w[base], w[base + 1]) : cmk(0.0, 0.0);
-    cplx g = wj;
-    bool alive = valid;
-    double a_re = 0.0, a_im = 0.0, n_re = 0.0, n_im = 0.0;   // lane q: q-th term
-    double absw = valid ? sqrt(wj.re * wj.re + wj.im * wj.im) : -1.0;
+    cplx* a_l = s_a[wv];
+    cplx* n_l = s_n[wv];
+    cplx uj[P], wj[P], g[P];
+    bool alive[P];
+    double absw[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        const int j = lane + 64 * s;
+        const bool valid = j < n_pts;
+        const int64_t base = ((int64_t)fit * n_pts + (valid ? j : 0)) * 2;
+        uj[s] = valid ? cmk(u[base], u[base + 1]) : cmk(0.0, 0.0);
+        wj[s] = valid ? cmk(w[base], w[base + 1]) : cmk(0.0, 0.0);
+        g[s] = wj[s];
+        alive[s] = valid;
+        absw[s] = valid ? sqrt(wj[s].re * wj[s].re + wj[s].im * wj[s].im) : -1.0;
+    }
     double scale;
-    int jsel = wave_argmax(absw, lane, scale);
+    int jsel = points_argmax<P>(absw, lane, scale);
     int p = 0;
     while (true) {
-        cplx a = cmk(shfl_d(g.re, jsel), shfl_d(g.im, jsel));
+        const cplx a = pick<P>(g, jsel >> 6, jsel & 63);
         if (!cfinite(a)) break;
-        cplx un = cmk(shfl_d(uj.re, jsel), shfl_d(uj.im, jsel));
-        if (lane == p) {
-            a_re = a.re; a_im = a.im; n_re = un.re; n_im = un.im;
-        }
+        const cplx un = pick<P>(uj, jsel >> 6, jsel & 63);
+        a_l[p] = a;                                 // every lane stores the same value
+        n_l[p] = un;
         ++p;
-        if (lane == jsel) alive = false;
-        if (__ballot(alive) == 0) break;
-        double err = -1.0;
-        bool bad = false;
-        if (alive) {
-            g = (a - g) / ((uj - un) * g);
+        bool any = false;
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            if (lane + 64 * s == jsel) alive[s] = false;
+            any = any || alive[s];
         }
-        cplx t = eval_lanes(uj, a_re, a_im, n_re, n_im, p);
-        if (alive) {
-            cplx r = wj - t;
-            err = fabs(r.re) + fabs(r.im);
-            bad = isnan(err);
+        if (__ballot(any) == 0) break;
+        double err[P];
+        bool bad = false;
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            err[s] = -1.0;
+            if (alive[s]) {
+                g[s] = (a - g[s]) / ((uj[s] - un) * g[s]);
+                const cplx r = wj[s] - eval_terms(uj[s], a_l, n_l, p);
+                err[s] = fabs(r.re) + fabs(r.im);
+                bad = bad || isnan(err[s]);
+            }
         }
         if (__ballot(bad) != 0) break;
         double emax;
-        jsel = wave_argmax(alive ? err : -1.0, lane, emax);
+        jsel = points_argmax<P>(err, lane, emax);
         if (!(emax > tol * scale)) break;
     }
-    const int64_t ob = ((int64_t)fit * n_pts + (valid ? lane : 0)) * 2;
-    if (valid) {
-        bool used = lane < p;
-        coef[ob] = used ? a_re : 0.0;
-        coef[ob + 1] = used ? a_im : 0.0;
-        node[ob] = used ? n_re : 0.0;
-        node[ob + 1] = used ? n_im : 0.0;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        const int j = lane + 64 * s;
+        if (j < n_pts) {
+            const int64_t ob = ((int64_t)fit * n_pts + j) * 2;
+            const bool used = j < p;
+            const cplx av = used ? a_l[j] : cmk(0.0, 0.0);
+            const cplx nv = used ? n_l[j] : cmk(0.0, 0.0);
+            coef[ob] = av.re;
+            coef[ob + 1] = av.im;
+            node[ob] = nv.re;
+            node[ob + 1] = nv.im;
+        }
     }
     if (lane == 0 && nterm) nterm[fit] = p;
 }
@@ -154,8 +198,13 @@ __global__ void k_gather_refs(int n_fit, const int* __restrict__ fit_s, const in
 void launch_thiele_fit(hipStream_t s, int n_fit, int n_pts, const double* u, const double* w, double tol,
                        double* coef, double* node, int* nterm) {
     if (n_fit <= 0) return;
-    hipLaunchKernelGGL(k_thiele_fit, dim3((n_fit + 3) / 4), dim3(256), 0, s, n_fit, n_pts, u, w, tol, coef,
-                       node, nterm);
+    const dim3 grid((n_fit + 3) / 4), block(256);
+    if (n_pts <= 64)
+        hipLaunchKernelGGL(k_thiele_fit<1>, grid, block, 0, s, n_fit, n_pts, u, w, tol, coef, node, nterm);
+    else if (n_pts <= 128)
+        hipLaunchKernelGGL(k_thiele_fit<2>, grid, block, 0, s, n_fit, n_pts, u, w, tol, coef, node, nterm);
+    else
+        hipLaunchKernelGGL(k_thiele_fit<4>, grid, block, 0, s, n_fit, n_pts, u, w, tol, coef, node, nterm);
 }
 
 void launch_thiele_eval(hipStream_t s, int n_fit, int n_pts, const double* coef, const double* node,

@@ -76,27 +76,45 @@ def generic_refs(eps: np.ndarray, n_occ: int, win_lo, n_re: int):
     return (np.arange(n_re) * x_max / (n_re - 1)).astype(np.float64)
 
 
-def refined_refs(eps: np.ndarray, n_occ: int, omega_core: float, n_core: int,
-                 n_val: int, delta_c: float, delta_v: float, core_eps=None):
-    """Real parts of the refined reference points (omega_C and omega_V).
+def refined_refs(eps: np.ndarray, n_occ: int, state_idx, win_lo, win_hi, n_core: int,
+                 n_val: int, delta_c: float = 10.0 / HARTREE_EV, delta_v: float = 30.0 / HARTREE_EV):
+    """Real parts of the refined reference points, omega_C then omega_V (Sec. 3.3).
 
-    ``omega_core`` is a typical QP energy of the core state; the core region is
-    centred on a typical core residue |eps_c - omega| (``core_eps`` defaults
-    to the lowest orbital), the valence region on |eps_F - omega|.  Points are
-    spaced evenly over [centre - delta, centre + delta], clipped at 0.
+    The paper centres one neighbourhood on a typical core residue
+    |eps_c - omega| and one on the residue at the Fermi level |eps_F - omega|,
+    with radii delta_c and delta_v, but prints neither the centres' omega nor
+    the radii.  Reading: omega is the mean centre of the QP windows and eps_c
+    the mean energy of the computed core states, so the core neighbourhood
+    holds the residues of the core band itself (near 0) and the valence one
+    the residues of the valence band seen from the core window.  Each region
+    gets its points evenly over [max(0, centre - delta), centre + delta]
+    (one point sits at the centre).  Defaults: delta_c = 10 eV,
+    delta_v = 30 eV.
     """
+    lo = np.asarray(win_lo, np.float64)
+    hi = np.asarray(win_hi, np.float64)
+    omega = 0.5 * (float(np.mean(lo)) + float(np.mean(hi)))
+    ec = float(np.mean(np.asarray(eps)[np.asarray(state_idx)]))
     ef = midgap(eps, n_occ)
-    ec = float(eps[0]) if core_eps is None else float(core_eps)
     out = []
-    for centre, n, d in ((abs(ec - omega_core), n_core, delta_c),
-                         (abs(ef - omega_core), n_val, delta_v)):
-        if n <= 0:
+    for centre, n, d in ((abs(ec - omega), n_core, delta_c), (abs(ef - omega), n_val, delta_v)):
+        if n < 0 or not d > 0:
+            raise ValueError("need n >= 0 and delta > 0")
+        if n == 0:
             continue
         if n == 1:
-            pts = np.array([centre])
+            out.append(np.array([centre]))
         else:
-            pts = np.linspace(centre - d, centre + d, n)
-        out.append(np.clip(pts, 0.0, None))
+            out.append(np.linspace(max(0.0, centre - d), centre + d, n))
     if not out:
         return np.zeros(0, dtype=np.float64)
     return np.concatenate(out).astype(np.float64)
+
+
+def cdwac_setting(eps: np.ndarray, n_occ: int, state_idx, win_lo, win_hi, n_core: int,
+                  n_val: int, n_im: int, n_freq: int, **deltas):
+    """Reference set of CD-WAC(N_core, N_valence, N_Im) (Sec. 3.3): N_Im evenly
+    strided imaginary nodes (all of them when N_Im = n_freq) and the refined
+    near-real points.  M = N_core + N_valence + N_Im."""
+    return (imag_ref_indices(n_freq, n_im),
+            refined_refs(eps, n_occ, state_idx, win_lo, win_hi, n_core, n_val, **deltas))

@@ -41,7 +41,7 @@ def test_grids():
     assert lo[0] == pytest.approx(-11.0) and hi[0] == pytest.approx(-9.0)
     x = grids.generic_refs(eps, 3, lo, 5)
     assert x[0] == 0.0 and x[-1] == pytest.approx(grids.midgap(eps, 3) + 11.0)
-    r = grids.refined_refs(eps, 3, -9.7, 4, 3, 0.5, 0.2)
+    r = grids.refined_refs(eps, 3, [0], lo, hi, 4, 3, 0.5, 0.2)
     assert len(r) == 7 and np.all(r >= 0)
 
 
@@ -51,3 +51,31 @@ def test_batch_specs():
     for sp in specs:
         assert 100 <= sp["n_mo"] <= 1200 and 1 <= sp["n_core"] <= 12
         assert sp["n_aux"] == round(3.3 * sp["n_mo"])
+
+
+def test_refined_reference_points():
+    """CD-WAC(N_core, N_valence, N_Im) reference sets (Sec. 3.3)."""
+    s = synth.make_workload("acene_nmo600")
+    lo, hi = grids.windows(s.eps, s.state_idx, 30.0)
+    ev = 1.0 / synth.HARTREE_EV
+    ri, rr = grids.cdwac_setting(s.eps, s.n_occ, s.state_idx, lo, hi, 20, 20, 200, 200)
+    assert len(ri) == 200 and np.array_equal(ri, np.arange(200)) and len(rr) == 40
+    core, val = rr[:20], rr[20:]
+    omega = 0.5 * (lo.mean() + hi.mean())
+    cc = abs(s.eps[s.state_idx].mean() - omega)
+    cv = abs(grids.midgap(s.eps, s.n_occ) - omega)
+    # the core neighbourhood starts at 0 (centre < delta_c), ends at centre + 10 eV
+    assert core[0] == 0.0 and core[-1] == pytest.approx(cc + 10 * ev)
+    assert val[0] == pytest.approx(cv - 30 * ev) and val[-1] == pytest.approx(cv + 30 * ev)
+    for part in (core, val):
+        assert np.all(np.diff(part) > 0) and np.allclose(np.diff(part), np.diff(part)[0])
+    # every valence residue seen from the core energies lies in the valence neighbourhood
+    occ_val = s.eps[s.n_states:s.n_occ]          # the cores are the lowest orbitals
+    res = np.abs(occ_val[:, None] - s.eps[s.state_idx][None, :])
+    assert res.min() >= val[0] and res.max() <= val[-1]
+    # one point sits at the centre; N = 0 drops the region
+    one = grids.refined_refs(s.eps, s.n_occ, s.state_idx, lo, hi, 1, 0)
+    assert one.shape == (1,) and one[0] == pytest.approx(cc)
+    assert len(grids.refined_refs(s.eps, s.n_occ, s.state_idx, lo, hi, 0, 0)) == 0
+    with pytest.raises(ValueError):
+        grids.refined_refs(s.eps, s.n_occ, s.state_idx, lo, hi, 2, 2, delta_c=0.0)
