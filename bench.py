@@ -102,6 +102,82 @@ def cpu_baseline(s, freq, n_re, n_states):
                        f"{len(freq)} real + {n_re} complex (4x) nodes = {t_job:.0f} s")}
 
 
+def scaling(sizes, cd_qp_max):
+    """Full CD against CD-WAC on one GPU as the system grows (Sec. 5,
+    scaling): N_mo in `sizes`, N_occ = N_mo / 6, N_aux = 3.3 N_mo, one core
+    state, 64 imaginary nodes, 24 Pade points, FP64 path on both sides.
+    CD-WAC: one cdwac_solve.  Full CD: cdwac_sigma_cd evaluates W directly at
+    every residue of one omega; its cost per QP solve is the imaginary-axis
+    part once plus the residue part per self-energy evaluation (as many as the
+    CD-WAC solve used).  Up to N_mo = cd_qp_max the full-CD QP energy is also
+    solved on the GPU (secant over cdwac_sigma_cd) to give CD-WAC's error."""
+    import torch
+    from paper_2305_15955_amd import cdwac, grids, synth
+    lib = cdwac.Cdwac(0)
+    rows = []
+    for n_mo in sizes:
+        n_occ = max(2, round(n_mo / 6))
+        n_aux = round(3.3 * n_mo)
+        k = n_occ * (n_mo - n_occ)
+        s = synth.make_system(n_mo, n_occ, n_aux, 1, math.sqrt(synth.SCREENING / k), seed=900 + n_mo)
+        freq, wts = grids.gauss_legendre_imag(64)
+        lo, hi = grids.windows(s.eps, s.state_idx, 30.0)
+        ref_im = grids.imag_ref_indices(64, 12)
+        ref_re = grids.generic_refs(s.eps, s.n_occ, lo, 12)
+        sysc, keep = lib.make_system(s)
+        prm, arrs = lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec="p64")
+        one, ones = grids.gauss_legendre_imag(1)
+        prm1, arrs1 = lib.make_params(one, ones, [0], ref_re, lo, hi, prec="p64")
+        lib.cdwac_solve(sysc, prm)                       # warm-up (allocations)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = lib.cdwac_solve(sysc, prm)[0]
+        t_wac = time.perf_counter() - t
+        qp = out["qp"]
+        lib.cdwac_sigma_cd(sysc, prm1, 0, qp)
+        t = time.perf_counter()
+        _, _, _, n_res = lib.cdwac_sigma_cd(sysc, prm, 0, qp)
+        t_call = time.perf_counter() - t
+        t = time.perf_counter()
+        lib.cdwac_sigma_cd(sysc, prm1, 0, qp)
+        t_res = time.perf_counter() - t
+        row = {"n_mo": n_mo, "n_aux": n_aux, "n_occ": n_occ, "K": k, "cdwac_s": t_wac,
+               "sigma_evals": out["n_evals"], "cd_residues": n_res, "cd_residue_part_s": t_res,
+               "cd_imag_part_s": max(t_call - t_res, 0.0),
+               "cd_qp_estimate_s": max(t_call - t_res, 0.0) + out["n_evals"] * t_res}
+        row["cd_over_cdwac"] = row["cd_qp_estimate_s"] / t_wac
+        if n_mo <= cd_qp_max:
+            e_n = float(s.eps[0])
+            f = lambda w: w - e_n - lib.cdwac_sigma_cd(sysc, prm, 0, w)[0] + float(out["sigma_x"])
+            w0, f0 = e_n, f(e_n)
+            w1 = w0 - f0
+            f1 = f(w1)
+            for _ in range(50):
+                w2 = w1 - f1 * (w1 - w0) / (f1 - f0)
+                w0, f0, w1 = w1, f1, w2
+                f1 = f(w1)
+                if abs(w1 - w0) < 1e-10:
+                    break
+            row["cd_qp_ev"] = w1 * synth.HARTREE_EV
+            row["cdwac_minus_cd_mev"] = (qp - w1) * synth.HARTREE_EV * 1e3
+        log(f"scaling N_mo={n_mo}: CD-WAC {t_wac:.3f} s, CD residue part {t_res:.3f} s x {out['n_evals']} "
+            f"evals ({n_res} residues)")
+        rows.append(row)
+        del keep
+    lib.close()
+
+    def slope(key):
+        big = rows[-3:]
+        x = np.log([r["n_mo"] for r in big])
+        y = np.log([r[key] for r in big])
+        return float(np.polyfit(x, y, 1)[0])
+    return {"metric": "full CD vs CD-WAC cost per core QP energy on one GPU (FP64 path)",
+            "unit": "s", "rows": rows,
+            "exponent_cdwac": slope("cdwac_s"), "exponent_cd": slope("cd_qp_estimate_s"),
+            "exponent_cd_per_eval": slope("cd_residue_part_s"),
+            "data": "synthetic (seeded Gaussian RI coefficients, no molecule)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,11 +188,18 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 GPU path")
     ap.add_argument("--rank-tol", type=float, default=1e-10,
                     help="imaginary-node decomposition tolerance of the 16-bit path (0: every node)")
+    ap.add_argument("--near-real-f64", action="store_true",
+                    help="16-bit modes: Pi at the near-real reference points on the FP64 path")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    ap.add_argument("--scaling", action="store_true",
+                    help="instead of the benchmark: full CD against CD-WAC as N_mo grows (one JSON line)")
     args = ap.parse_args()
+    if args.scaling:
+        print(json.dumps(scaling([60, 120, 240, 480, 960], 240)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
               "multi-GPU mode in this build", file=sys.stderr)
@@ -143,7 +226,8 @@ def main():
     def params(prec, mlp):
         return lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec=prec,
                                pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4 / synth.HARTREE_EV,
-                               freq_rank_tol=args.rank_tol if prec != "p64" else 0.0)
+                               freq_rank_tol=args.rank_tol if prec != "p64" else 0.0,
+                               near_real_f64=args.near_real_f64 and prec != "p64")
 
     sysc, keep = lib.make_system(s, o_ia_dev=o_ia, o_nm_dev=o_nm)
     lib.cdwac_set_timing(True)
@@ -178,7 +262,8 @@ def main():
            "config": {"workload": args.workload, "n_aux": s.n_aux, "n_mo": s.n_mo, "n_occ": s.n_occ,
                       "n_states": s.n_states, "n_freq": len(freq), "n_pade": len(ref_im) + len(ref_re),
                       "contraction_precision": args.prec, "mlp_seed": use_mlp,
-                      "freq_rank_tol": args.rank_tol if args.prec != "p64" else 0.0}}
+                      "freq_rank_tol": args.rank_tol if args.prec != "p64" else 0.0,
+                      "near_real_f64": bool(args.near_real_f64 and args.prec != "p64")}}
 
     # roofline of the dominant kernel: the polarizability contraction, one
     # launch per batch of frequency planes; achieved = algorithmic flops of
@@ -207,6 +292,10 @@ def main():
                        "launches": n_launch, "algorithmic_flop_per_launch": flops,
                        "launch_ms": launch_s * 1e3,
                        "mfma_issued_frac": issued / launch_s / PEAK[args.prec]}
+    if res["config"]["near_real_f64"]:
+        # the polarizability stage then mixes the 16-bit and the FP64 kernel:
+        # no single-kernel roofline
+        res["roofline"] = None
     res["stages_ms"] = stages
     # spectral function (Sec. 4) on 5000 points per state over a 50 eV range,
     # from the prepared tables of the last step

@@ -115,6 +115,17 @@ typedef struct {
                                   sup-norm error <= tol relative to each function's
                                   maximum; falls back to every node if the range check
                                   fails); 0 uses every node.  Ignored by CDWAC_P64.  [0, 1) */
+    int32_t fit_all;           /* 1: fit W^c_nm of every m (all (n, m) pairs); 0: only the
+                                  m whose residue can enter the window (Eq. ffact).  The
+                                  QP results are the same; 1 is the heavier fit load.     */
+    int32_t near_real_f64;     /* 16-bit modes: 1 computes Pi at the near-real reference
+                                  points on the FP64 path (the imaginary nodes stay 16-bit).
+                                  There W sits within eta_ref of RPA poles Omega_s of up to
+                                  ~10 Ha (core excitations); a relative error d of Pi moves
+                                  them by ~d*Omega, i.e. by d*Omega/eta_ref of the pole
+                                  width, so 16-bit Pi leaves W good to only ~1e-4..1e-2
+                                  there.  Costs FP64 matrix-core time for 2*n_ref_re planes
+                                  and an FP64 copy of O^{ia}.                              */
 } cdwac_params;
 
 /* Result for one state (host, written by cdwac_qp / cdwac_solve). */
@@ -156,11 +167,38 @@ int cdwac_qp(cdwac_ctx *ctx, const double *vxc, cdwac_state_out *out);
 int cdwac_solve(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm,
                 cdwac_state_out *out);
 
+/* A batch of independent systems of uneven size (Sec. 3.4 for each): Pi,
+ * eps^-1 and W of every system in turn (each a full-width launch of its own
+ * shape), then the greedy Thiele fits of all systems in ONE launch and the QP
+ * roots of all states of all systems in ONE launch.
+ * sys, prm: host arrays [n_sys]; every prm[j] must have the same
+ * n_ref_im + n_ref_re and pade_tol (the fits share one launch).
+ * out: host [sum of sys[j].n_states], the states of system 0 first.
+ * The batch's W tables, fits and QP inputs live in device memory the context
+ * allocates (kept for reuse, freed by cdwac_ctx_destroy); the per-system work
+ * uses the workspace as cdwac_prepare does.  The context is left unprepared
+ * (cdwac_qp/cdwac_sigma need a new cdwac_prepare).  Every argument is checked
+ * before any launch; returns CDWAC_WNOROOT if a state has no root. */
+int cdwac_solve_batch(cdwac_ctx *ctx, int32_t n_sys, const cdwac_system *sys, const cdwac_params *prm,
+                      cdwac_state_out *out);
+
 /* Re Sigma_n(omega) = Sigma^x + Re R_n - I_n (Eq. cdselfe) at n_omega
  * frequencies per state.  omega, sigma: device [n_states][n_omega].
  * Also writes I_n and R_n when i_term / r_term are non-NULL (same shape). */
 int cdwac_sigma(cdwac_ctx *ctx, int32_t n_omega, const double *omega, double *sigma,
                 double *i_term, double *r_term);
+
+/* Sigma_n(omega) by full contour deformation (Sec. 2.3, Eqs. Rn_term,
+ * In_term, cdselfe): W^c_nm evaluated directly at every residue
+ * |eps_m - omega| + i*eta with f_m(omega) != 0 (Eq. ffact), i.e. one complex
+ * polarizability, inversion and contraction per residue -- the O(N^5) method
+ * CD-WAC replaces.  state: index into sys->state_idx; the imaginary grid and
+ * the precision come from prm (its Pade reference set is not used).
+ * out: host [3] = {Sigma_n, R_n, I_n} (Ha).  n_res: host, the residue count
+ * (may be NULL).  At most 256 residues per call.  Leaves the context
+ * unprepared.  Synchronous. */
+int cdwac_sigma_cd(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm, int32_t state,
+                   double omega, double *out, int32_t *n_res);
 
 /* Diagonal spectral function (Sec. 4): with the complex self-energy
  * Sigma_n = Sigma^x + R_n - I_n (the imaginary part comes from the residue

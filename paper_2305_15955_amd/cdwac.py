@@ -49,7 +49,8 @@ class CdwacParams(ctypes.Structure):
                 ("pade_tol", ctypes.c_double), ("win_lo", _f64p), ("win_hi", _f64p),
                 ("qp_tol", ctypes.c_double), ("qp_maxit", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("use_mlp_seed", ctypes.c_int32), ("mlp_accept", ctypes.c_double),
-                ("freq_rank_tol", ctypes.c_double)]
+                ("freq_rank_tol", ctypes.c_double), ("fit_all", ctypes.c_int32),
+                ("near_real_f64", ctypes.c_int32)]
 
 
 class CdwacStateOut(ctypes.Structure):
@@ -72,6 +73,10 @@ _SIGNATURES = {
     "cdwac_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "cdwac_prepare": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams)]),
     "cdwac_qp": (ctypes.c_int, [_vp, _f64p, ctypes.POINTER(CdwacStateOut)]),
+    "cdwac_sigma_cd": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams),
+                                      ctypes.c_int32, ctypes.c_double, _f64p, _i32p]),
+    "cdwac_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(CdwacSystem),
+                                         ctypes.POINTER(CdwacParams), ctypes.POINTER(CdwacStateOut)]),
     "cdwac_solve": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams),
                                    ctypes.POINTER(CdwacStateOut)]),
     "cdwac_sigma": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
@@ -236,7 +241,8 @@ class Cdwac:
     @staticmethod
     def make_params(freq, weight, ref_im_idx, ref_re, win_lo, win_hi, eta=1e-3, eta_ref=1e-3,
                     pade_tol=1e-9, qp_tol=1e-10, qp_maxit=100, prec="p64", use_mlp_seed=False,
-                    mlp_accept=0.0, freq_rank_tol=0.0):
+                    mlp_accept=0.0, freq_rank_tol=0.0, fit_all=False,
+                    near_real_f64=False):
         arrs = dict(freq=np.ascontiguousarray(freq, np.float64),
                     weight=np.ascontiguousarray(weight, np.float64),
                     ref_im=np.ascontiguousarray(ref_im_idx, np.int32),
@@ -252,7 +258,8 @@ class Cdwac:
                         win_hi=_np_ptr(arrs["hi"], ctypes.c_double), qp_tol=qp_tol,
                         qp_maxit=qp_maxit, prec=PREC[prec] if isinstance(prec, str) else int(prec),
                         use_mlp_seed=int(bool(use_mlp_seed)), mlp_accept=mlp_accept,
-                        freq_rank_tol=freq_rank_tol)
+                        freq_rank_tol=freq_rank_tol, fit_all=int(bool(fit_all)),
+                        near_real_f64=int(bool(near_real_f64)))
         return p, arrs
 
     # -- entry points -----------------------------------------------------
@@ -281,6 +288,31 @@ class Cdwac:
         rc = self.lib.cdwac_solve(self.ctx, ctypes.byref(sysc), ctypes.byref(prm), out)
         _check(self.ctx, rc, allow_warn=True)
         return _outs(out)
+
+    def cdwac_solve_batch(self, systems, params):
+        """systems, params: lists of CdwacSystem / CdwacParams (one per system)
+        -> list of per-system lists of state results."""
+        n = len(systems)
+        sa = (CdwacSystem * n)(*systems)
+        pa = (CdwacParams * n)(*params)
+        counts = [int(x.n_states) for x in systems]
+        out = (CdwacStateOut * sum(counts))()
+        rc = self.lib.cdwac_solve_batch(self.ctx, n, sa, pa, out)
+        _check(self.ctx, rc, allow_warn=True)
+        flat = _outs(out)
+        res, k = [], 0
+        for c in counts:
+            res.append(flat[k:k + c])
+            k += c
+        return res
+
+    def cdwac_sigma_cd(self, sysc, prm, state: int, omega: float):
+        """Full-CD Sigma_n(omega) -> (Sigma, R_n, I_n, residue count)."""
+        out = np.zeros(3, np.float64)
+        nr = ctypes.c_int32(0)
+        _check(self.ctx, self.lib.cdwac_sigma_cd(self.ctx, ctypes.byref(sysc), ctypes.byref(prm), int(state),
+                                                 float(omega), _np_ptr(out, ctypes.c_double), ctypes.byref(nr)))
+        return float(out[0]), float(out[1]), float(out[2]), int(nr.value)
 
     def cdwac_sigma(self, omega, terms: bool = False):
         """omega: [n_states, n_omega] (Ha) -> Re Sigma (and I, R) as numpy."""

@@ -36,12 +36,13 @@ struct Plan {
     int n_mo, n_occ, n_virt, n_aux, S, n_freq, n_im, n_re, n_pts, n_f, prec;
     int npad, cpad, cfpad, ni, n_fit, nblk, nb, n_tpi, n_tw, n_twf;
     int n_imp;    // imaginary-axis planes (every node, or the skeleton nodes)
+    bool nr64;    // 16-bit mode with the near-real planes of Pi on the FP64 path
     int64_t K, kpad;
     // persistent regions
     Region eps, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
         fit_m, w_im, w_re, coef, node, nterm, qpout, err;
     // transient regions (prepare only)
-    Region zr, zi, part, idflag, amax, sf, cw, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
+    Region zr, zi, part, idflag, amax, sf, cw, cw64, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
         bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w, x32, yh, yl, t_pi, t_w,
         t_wf, pmap, imnode, imrest, tmat, rowsum;
     size_t total = 0;
@@ -89,6 +90,9 @@ struct cdwac_ctx {
     // MLP scratch
     void* mlp_scratch = nullptr;
     size_t mlp_scratch_bytes = 0;
+    // tables of a batch of systems (cdwac_solve_batch)
+    void* batch = nullptr;
+    size_t batch_bytes = 0;
     // stage timing: segments of kernels bracketed by event pairs on the stream
     bool timing = false;
     struct Seg {
@@ -190,6 +194,9 @@ int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p
     if (p->use_mlp_seed && !(p->mlp_accept >= 0.0)) return fail(ctx, CDWAC_EINVAL, "mlp_accept must be >= 0");
     if (!(p->freq_rank_tol >= 0.0 && p->freq_rank_tol < 1.0))
         return fail(ctx, CDWAC_EINVAL, "freq_rank_tol must be in [0, 1)");
+    if (p->fit_all != 0 && p->fit_all != 1) return fail(ctx, CDWAC_EINVAL, "fit_all must be 0 or 1");
+    if (p->near_real_f64 != 0 && p->near_real_f64 != 1)
+        return fail(ctx, CDWAC_EINVAL, "near_real_f64 must be 0 or 1");
     return CDWAC_OK;
 }
 
@@ -350,7 +357,12 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     // fit list
     std::vector<int> m0(P.S), m1(P.S), off(P.S), fs, fm;
     for (int j = 0; j < P.S; ++j) {
-        fit_range(s->eps, P.n_mo, P.n_occ, p->win_lo[j] - kFitMargin, p->win_hi[j] + kFitMargin, m0[j], m1[j]);
+        if (p->fit_all) {
+            m0[j] = 0;
+            m1[j] = P.n_mo;
+        } else {
+            fit_range(s->eps, P.n_mo, P.n_occ, p->win_lo[j] - kFitMargin, p->win_hi[j] + kFitMargin, m0[j], m1[j]);
+        }
         off[j] = (int)fs.size();
         for (int m = m0[j]; m < m1[j]; ++m) {
             fs.push_back(j);
@@ -372,6 +384,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
         hs->fit_m = fm;
     }
     const bool f64 = P.prec == CDWAC_P64;
+    P.nr64 = !f64 && p->near_real_f64 && P.n_re > 0;
     const int64_t n2 = (int64_t)P.npad * P.npad;
     const int64_t blk = (int64_t)kNb * kNb;
     // persistent
@@ -412,9 +425,9 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     // scales: [0] x, [1] B, cfac[F], pi_unscale[F], lam_scale[F], w_unscale[F]
     add(P, P.sf, sizeof(double) * (2 + 4 * (size_t)P.n_f));
     add(P, P.cw, (f64 ? sizeof(double) : sizeof(float)) * (size_t)P.n_f * P.kpad);
-    if (f64) {
-        add(P, P.x64, sizeof(double) * (size_t)P.npad * P.kpad);
-    } else {
+    add(P, P.cw64, P.nr64 ? sizeof(double) * (size_t)P.n_f * P.kpad : 0);
+    if (f64 || P.nr64) add(P, P.x64, sizeof(double) * (size_t)P.npad * P.kpad);
+    if (!f64) {
         // one-product Pi (CDWAC_F16) needs no lo planes of X and Y
         const size_t n_pl = P.prec == CDWAC_F16 ? 1 : 2;
         add(P, P.xh, sizeof(uint16_t) * (size_t)P.npad * P.kpad);
@@ -611,6 +624,7 @@ void cdwac_ctx_destroy(cdwac_ctx* ctx) {
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
     if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
+    if (ctx->batch) (void)hipFree(ctx->batch);
     delete ctx;
 }
 
@@ -631,7 +645,14 @@ int cdwac_set_workspace(cdwac_ctx* ctx, void* dev_ptr, size_t bytes) {
 }
 
 namespace {
-int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, bool allow_id);
+// Destination of a batched preparation's fit inputs: the reference data of the
+// system's fits go to u, w (fits are then left to one launch for the batch).
+struct FitSink {
+    double* u = nullptr;
+    double* w = nullptr;
+};
+int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, bool allow_id,
+                 const FitSink* sink = nullptr);
 }
 
 int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm) {
@@ -644,7 +665,8 @@ int cdwac_prepare(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* p
 }
 
 namespace {
-int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, bool allow_id) {
+int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, bool allow_id,
+                 const FitSink* sink) {
     HIPCK(hipSetDevice(ctx->device));
     HostState hs;
     Plan P = make_plan(sys, prm, &hs, allow_id);
@@ -739,11 +761,11 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     launch_absmax(st, sys->o_nm, P.n_mo, P.S * P.n_aux, P.n_mo, amax + 1, err);
     launch_weights(st, at<double>(ctx, P.eps), P.n_occ, P.n_virt, sys->spin, at<double>(ctx, P.zr),
                    at<double>(ctx, P.zi), at<int>(ctx, P.part), P.n_f, P.kpad,
-                   f64 ? at<double>(ctx, P.cw) : nullptr, f64 ? nullptr : at<float>(ctx, P.cw), amax + 2);
+                   f64 ? at<double>(ctx, P.cw) : (P.nr64 ? at<double>(ctx, P.cw64) : nullptr),
+                   f64 ? nullptr : at<float>(ctx, P.cw), amax + 2);
     LAUNCHCK();
-    if (f64) {
-        launch_pad_f64(st, sys->o_ia, P.K, P.n_aux, P.K, at<double>(ctx, P.x64), P.npad, P.kpad);
-    } else {
+    if (f64 || P.nr64) launch_pad_f64(st, sys->o_ia, P.K, P.n_aux, P.K, at<double>(ctx, P.x64), P.npad, P.kpad);
+    if (!f64) {
         launch_scales_pi(st, amax, P.n_f, sf);
         launch_split_panel(st, et, sys->o_ia, 0, 1, P.K, P.n_aux, P.K, sf, at<uint16_t>(ctx, P.xh),
                            pi_split ? at<uint16_t>(ctx, P.xl) : nullptr, at<float>(ctx, P.x32), P.npad, P.kpad);
@@ -763,8 +785,9 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
         TRY(seg_end(ctx));
     } else {
         const int* pm = at<int>(ctx, P.pmap);
-        for (int f0 = 0; f0 < P.n_f; f0 += P.nb) {
-            const int nfb = std::min(P.nb, P.n_f - f0);
+        const int n_pi16 = P.nr64 ? P.n_imp : P.n_f;   // planes on the 16-bit path
+        for (int f0 = 0; f0 < n_pi16; f0 += P.nb) {
+            const int nfb = std::min(P.nb, n_pi16 - f0);
             TRY(seg_begin(ctx, 7));
             launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, pm + f0, nfb,
                             at<uint16_t>(ctx, P.yh), pi_split ? at<uint16_t>(ctx, P.yl) : nullptr);
@@ -775,6 +798,14 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
                            at<uint16_t>(ctx, pi_split ? P.xl : P.xh), at<uint16_t>(ctx, P.yh),
                            at<uint16_t>(ctx, pi_split ? P.yl : P.yh), at<int2>(ctx, P.t_pi), P.n_tpi, pi_unscale,
                            at<int>(ctx, P.idflag), at<double>(ctx, P.E));
+            LAUNCHCK();
+            TRY(seg_end(ctx));
+        }
+        if (P.nr64) {
+            TRY(seg_begin(ctx, 1));
+            launch_pi_f64(st, P.npad, P.kpad, 2 * P.n_re, at<double>(ctx, P.x64),
+                          at<double>(ctx, P.cw64) + (size_t)P.n_imp * P.kpad, at<int>(ctx, P.idflag) + P.n_imp,
+                          at<double>(ctx, P.E) + (size_t)P.n_imp * n2);
             LAUNCHCK();
             TRY(seg_end(ctx));
         }
@@ -851,14 +882,17 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
                               hipMemcpyDeviceToDevice, st));
     // (a5) greedy Thiele fits over F_wac
     if (P.n_fit > 0) {
+        double* ru = sink ? sink->u : at<double>(ctx, P.ref_u);
+        double* rw = sink ? sink->w : at<double>(ctx, P.ref_w);
         launch_gather_refs(st, P.n_fit, at<int>(ctx, P.fit_s), at<int>(ctx, P.fit_m), P.n_mo, P.n_freq,
                            at<double>(ctx, P.w_im), at<double>(ctx, P.w_re), at<double>(ctx, P.freq),
-                           at<int>(ctx, P.ref_im), P.n_im, at<double>(ctx, P.ref_re), P.n_re, prm->eta_ref,
-                           at<double>(ctx, P.ref_u), at<double>(ctx, P.ref_w));
+                           at<int>(ctx, P.ref_im), P.n_im, at<double>(ctx, P.ref_re), P.n_re, prm->eta_ref, ru, rw);
         LAUNCHCK();
-        launch_thiele_fit(st, P.n_fit, P.n_pts, at<double>(ctx, P.ref_u), at<double>(ctx, P.ref_w), prm->pade_tol,
-                          at<double>(ctx, P.coef), at<double>(ctx, P.node), at<int>(ctx, P.nterm));
-        LAUNCHCK();
+        if (!sink) {
+            launch_thiele_fit(st, P.n_fit, P.n_pts, ru, rw, prm->pade_tol, at<double>(ctx, P.coef),
+                              at<double>(ctx, P.node), at<int>(ctx, P.nterm));
+            LAUNCHCK();
+        }
     }
     TRY(seg_end(ctx));
     int herr[4] = {0, 0, 0, 0};
@@ -876,7 +910,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
         const double dmax = sys->eps[P.n_mo - 1] - sys->eps[0];
         const double wmax = *std::max_element(prm->freq, prm->freq + P.n_freq);
         const double om_bound = std::sqrt(dmax * dmax + (wmax * wmax + dmax * dmax) * g);
-        if (!(om_bound <= hs.omega_hi)) return prepare_impl(ctx, sys, prm, false);
+        if (!(om_bound <= hs.omega_hi)) return prepare_impl(ctx, sys, prm, false, sink);
     }
     if (herr[0] & 1) return fail(ctx, CDWAC_ENOTPD, "zero or non-finite pivot while inverting eps = I - Pi");
     ctx->hs = hs;
@@ -915,6 +949,251 @@ int cdwac_solve(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm
     if (!out) return fail(ctx, CDWAC_EINVAL, "out is NULL");
     TRY(cdwac_prepare(ctx, sys, prm));
     return cdwac_qp(ctx, nullptr, out);
+}
+
+namespace {
+// Per-system tables of a batch, copied out of the workspace after the
+// system's preparation (offsets into the batch buffer).
+struct BatchSys {
+    size_t w_im, eps, freq, weight, state_idx, sigx, vxc, win_lo, win_hi, m0, m1, fit_off;
+    int fit0;
+    QpArgs args;
+};
+
+// Context-owned device buffer of at least `bytes` (grown on demand, kept).
+int ensure_batch(cdwac_ctx* ctx, size_t bytes) {
+    if (ctx->batch_bytes >= bytes) return CDWAC_OK;
+    if (ctx->batch) {
+        HIPCK(hipStreamSynchronize(ctx->stream));
+        HIPCK(hipFree(ctx->batch));
+        ctx->batch = nullptr;
+        ctx->batch_bytes = 0;
+    }
+    if (hipMalloc(&ctx->batch, bytes) != hipSuccess) {
+        ctx->batch = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, CDWAC_ENOMEM, "cannot allocate %zu bytes of batch tables", bytes);
+    }
+    ctx->batch_bytes = bytes;
+    return CDWAC_OK;
+}
+
+size_t bump(size_t& total, size_t bytes) {
+    size_t off = total;
+    total += (bytes + 255) / 256 * 256;
+    return off;
+}
+
+int copy_d2d(cdwac_ctx* ctx, size_t dst_off, const void* src, size_t bytes) {
+    if (bytes == 0) return CDWAC_OK;
+    HIPCK(hipMemcpyAsync((char*)ctx->batch + dst_off, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    return CDWAC_OK;
+}
+}  // namespace
+
+int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, const cdwac_params* prm,
+                      cdwac_state_out* out) {
+    if (!ctx) return CDWAC_EINVAL;
+    ctx->prepared = false;
+    if (n_sys < 1 || !sys || !prm || !out) return fail(ctx, CDWAC_EINVAL, "bad batch arguments");
+    // every argument is checked before any launch
+    size_t ws_max = 0;
+    int n_pts = 0, s_tot = 0, f_tot = 0;
+    std::vector<int> n_fit(n_sys);
+    for (int j = 0; j < n_sys; ++j) {
+        TRY(validate_system(ctx, &sys[j]));
+        TRY(validate_params(ctx, &sys[j], &prm[j]));
+        if (prm[j].use_mlp_seed && !ctx->have_mlp)
+            return fail(ctx, CDWAC_EINVAL, "system %d: use_mlp_seed set but no model installed", j);
+        const int m = prm[j].n_ref_im + prm[j].n_ref_re;
+        if (j == 0) n_pts = m;
+        if (m != n_pts || prm[j].pade_tol != prm[0].pade_tol)
+            return fail(ctx, CDWAC_EINVAL, "system %d: every system needs the same Pade point count and pade_tol", j);
+        const Plan P = make_plan(&sys[j], &prm[j], nullptr);
+        ws_max = std::max(ws_max, P.total);
+        n_fit[j] = P.n_fit;
+        s_tot += P.S;
+        f_tot += P.n_fit;
+    }
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // batch buffer layout
+    std::vector<BatchSys> bs(n_sys);
+    size_t total = 0;
+    for (int j = 0; j < n_sys; ++j) {
+        const cdwac_system& y = sys[j];
+        const int S = y.n_states;
+        BatchSys& b = bs[j];
+        b.w_im = bump(total, sizeof(double) * (size_t)S * y.n_mo * prm[j].n_freq);
+        b.eps = bump(total, sizeof(double) * y.n_mo);
+        b.freq = bump(total, sizeof(double) * prm[j].n_freq);
+        b.weight = bump(total, sizeof(double) * prm[j].n_freq);
+        b.state_idx = bump(total, sizeof(int) * S);
+        b.sigx = bump(total, sizeof(double) * S);
+        b.vxc = bump(total, sizeof(double) * S);
+        b.win_lo = bump(total, sizeof(double) * S);
+        b.win_hi = bump(total, sizeof(double) * S);
+        b.m0 = bump(total, sizeof(int) * S);
+        b.m1 = bump(total, sizeof(int) * S);
+        b.fit_off = bump(total, sizeof(int) * S);
+    }
+    const size_t fits = (size_t)std::max(f_tot, 1) * n_pts * 2 * sizeof(double);
+    const size_t o_u = bump(total, fits), o_w = bump(total, fits), o_coef = bump(total, fits),
+                 o_node = bump(total, fits);
+    const size_t o_nterm = bump(total, sizeof(int) * std::max(f_tot, 1));
+    const size_t o_args = bump(total, sizeof(QpArgs) * n_sys);
+    const size_t o_map = bump(total, sizeof(int2) * s_tot);
+    const size_t o_out = bump(total, sizeof(QpOut) * s_tot);
+    TRY(ensure_batch(ctx, total));
+    TRY(ensure_workspace(ctx, ws_max));
+    char* base = (char*)ctx->batch;
+    double ms[CDWAC_N_STAGES] = {};
+    int32_t cnt[CDWAC_N_STAGES] = {};
+    // (a0)-(a4) per system; the fits' reference data go to the batch buffer
+    int fit0 = 0;
+    for (int j = 0; j < n_sys; ++j) {
+        const size_t fo = (size_t)fit0 * n_pts * 2;
+        FitSink sink{(double*)(base + o_u) + fo, (double*)(base + o_w) + fo};
+        const int rc = prepare_impl(ctx, &sys[j], &prm[j], true, &sink);
+        ctx->prepared = false;             // the workspace holds no fits
+        if (rc != CDWAC_OK) return rc;
+        for (int i = 0; i < CDWAC_N_STAGES; ++i) {
+            ms[i] += ctx->stage_ms[i];
+            cnt[i] += ctx->stage_n[i];
+        }
+        const Plan& P = ctx->plan;
+        BatchSys& b = bs[j];
+        TRY(copy_d2d(ctx, b.w_im, at<double>(ctx, P.w_im), sizeof(double) * (size_t)P.S * P.n_mo * P.n_freq));
+        TRY(copy_d2d(ctx, b.eps, at<double>(ctx, P.eps), sizeof(double) * P.n_mo));
+        TRY(copy_d2d(ctx, b.freq, at<double>(ctx, P.freq), sizeof(double) * P.n_freq));
+        TRY(copy_d2d(ctx, b.weight, at<double>(ctx, P.weight), sizeof(double) * P.n_freq));
+        TRY(copy_d2d(ctx, b.state_idx, at<int>(ctx, P.state_idx), sizeof(int) * P.S));
+        TRY(copy_d2d(ctx, b.sigx, at<double>(ctx, P.sigx), sizeof(double) * P.S));
+        TRY(copy_d2d(ctx, b.vxc, at<double>(ctx, P.vxc), sizeof(double) * P.S));
+        TRY(copy_d2d(ctx, b.win_lo, at<double>(ctx, P.win_lo), sizeof(double) * P.S));
+        TRY(copy_d2d(ctx, b.win_hi, at<double>(ctx, P.win_hi), sizeof(double) * P.S));
+        TRY(copy_d2d(ctx, b.m0, at<int>(ctx, P.m0), sizeof(int) * P.S));
+        TRY(copy_d2d(ctx, b.m1, at<int>(ctx, P.m1), sizeof(int) * P.S));
+        TRY(copy_d2d(ctx, b.fit_off, at<int>(ctx, P.fit_off), sizeof(int) * P.S));
+        QpArgs a = qp_args(ctx);
+        a.eps = (const double*)(base + b.eps);
+        a.freq = (const double*)(base + b.freq);
+        a.weight = (const double*)(base + b.weight);
+        a.w_im = (const double*)(base + b.w_im);
+        a.coef = (const double*)(base + o_coef) + fo;
+        a.node = (const double*)(base + o_node) + fo;
+        a.nterm = (const int*)(base + o_nterm) + fit0;
+        a.fit_off = (const int*)(base + b.fit_off);
+        a.m0 = (const int*)(base + b.m0);
+        a.m1 = (const int*)(base + b.m1);
+        a.state_idx = (const int*)(base + b.state_idx);
+        a.sigx = (const double*)(base + b.sigx);
+        a.vxc = (const double*)(base + b.vxc);
+        a.win_lo = (const double*)(base + b.win_lo);
+        a.win_hi = (const double*)(base + b.win_hi);
+        b.args = a;
+        b.fit0 = fit0;
+        fit0 += n_fit[j];
+    }
+    ctx->segs.clear();
+    ctx->pool_used = 0;
+    for (int i = 0; i < CDWAC_N_STAGES; ++i) {
+        ctx->stage_ms[i] = ms[i];
+        ctx->stage_n[i] = cnt[i];
+    }
+    // (a5) the greedy fits of every system in one launch
+    TRY(seg_begin(ctx, 5));
+    launch_thiele_fit(st, f_tot, n_pts, (const double*)(base + o_u), (const double*)(base + o_w), prm[0].pade_tol,
+                      (double*)(base + o_coef), (double*)(base + o_node), (int*)(base + o_nterm));
+    LAUNCHCK();
+    TRY(seg_end(ctx));
+    // (a6)-(a8) the QP roots of every state in one launch
+    std::vector<QpArgs> args(n_sys);
+    std::vector<int2> map;
+    map.reserve(s_tot);
+    for (int j = 0; j < n_sys; ++j) {
+        args[j] = bs[j].args;
+        for (int q = 0; q < sys[j].n_states; ++q) map.push_back(make_int2(j, q));
+    }
+    TRY(upload(ctx, (QpArgs*)(base + o_args), args.data(), args.size()));
+    TRY(upload(ctx, (int2*)(base + o_map), map.data(), map.size()));
+    TRY(seg_begin(ctx, 6));
+    launch_qp_batch(st, s_tot, (const QpArgs*)(base + o_args), (const int2*)(base + o_map), (QpOut*)(base + o_out));
+    LAUNCHCK();
+    TRY(seg_end(ctx));
+    static_assert(sizeof(QpOut) == sizeof(cdwac_state_out), "output layout");
+    HIPCK(hipMemcpyAsync(out, base + o_out, sizeof(QpOut) * s_tot, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    TRY(seg_collect(ctx));
+    for (int j = 0; j < s_tot; ++j)
+        if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
+    return CDWAC_OK;
+}
+
+int cdwac_sigma_cd(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, int32_t state, double omega,
+                   double* out, int32_t* n_res) {
+    if (!ctx) return CDWAC_EINVAL;
+    ctx->prepared = false;
+    TRY(validate_system(ctx, sys));
+    TRY(validate_params(ctx, sys, prm));
+    if (state < 0 || state >= sys->n_states) return fail(ctx, CDWAC_EINVAL, "state %d out of range", state);
+    if (!std::isfinite(omega)) return fail(ctx, CDWAC_EINVAL, "omega is not finite");
+    if (!out) return fail(ctx, CDWAC_EINVAL, "out is NULL");
+    const int n_mo = sys->n_mo, n_occ = sys->n_occ;
+    const double ef = std::isnan(sys->eps_fermi) ? 0.5 * (sys->eps[n_occ - 1] + sys->eps[n_occ]) : sys->eps_fermi;
+    auto theta = [](double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? 0.0 : 0.5); };
+    // residues of Eq. (Rn_term): every m with f_m(omega) != 0 (Eq. ffact)
+    std::vector<int> rm;
+    std::vector<double> rf, rx;
+    for (int m = 0; m < n_mo; ++m) {
+        const double em = sys->eps[m];
+        const double fm = -theta(ef - em) * theta(em - omega) + theta(em - ef) * theta(omega - em);
+        if (fm == 0.0) continue;
+        rm.push_back(m);
+        rf.push_back(fm);
+        rx.push_back(std::fabs(em - omega));
+    }
+    if (rm.empty()) {          // no residue: one placeholder point with weight 0
+        rm.push_back(0);
+        rf.push_back(0.0);
+        rx.push_back(0.0);
+    }
+    const int nr = (int)rm.size();
+    if (nr > kMaxPade) return fail(ctx, CDWAC_EINVAL, "%d residues exceed the %d near-real planes of one call", nr, kMaxPade);
+    if (n_res) *n_res = rf[0] == 0.0 && nr == 1 ? 0 : nr;
+    // one state; the residues are the near-real points (eta_ref = eta); every m fitted
+    cdwac_system s1 = *sys;
+    s1.n_states = 1;
+    s1.state_idx = sys->state_idx + state;
+    s1.o_nm = sys->o_nm + (size_t)state * sys->n_aux * n_mo;
+    s1.vxc = sys->vxc ? sys->vxc + state : nullptr;
+    s1.eps_fermi = ef;
+    cdwac_params p1 = *prm;
+    p1.n_ref_im = 0;
+    p1.ref_im_idx = nullptr;
+    p1.n_ref_re = nr;
+    p1.ref_re = rx.data();
+    p1.eta_ref = prm->eta > 0.0 ? prm->eta : 1e-3;
+    p1.win_lo = prm->win_lo + state;
+    p1.win_hi = prm->win_hi + state;
+    p1.use_mlp_seed = 0;
+    p1.fit_all = 1;
+    const int rc = prepare_impl(ctx, &s1, &p1, true);
+    ctx->prepared = false;             // a residue set, not a CD-WAC model
+    if (rc != CDWAC_OK) return rc;
+    hipStream_t st = ctx->stream;
+    const size_t o_rm = 0, o_rf = (sizeof(int) * nr + 255) / 256 * 256, o_out = o_rf + (sizeof(double) * nr + 255) / 256 * 256;
+    TRY(ensure_batch(ctx, o_out + 256));
+    char* base = (char*)ctx->batch;
+    TRY(upload(ctx, (int*)(base + o_rm), rm.data(), nr));
+    TRY(upload(ctx, (double*)(base + o_rf), rf.data(), nr));
+    const Plan& P = ctx->plan;
+    launch_sigma_direct(st, qp_args(ctx), omega, at<double>(ctx, P.w_re), nr, (const int*)(base + o_rm),
+                        (const double*)(base + o_rf), (double*)(base + o_out));
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(out, base + o_out, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    return CDWAC_OK;
 }
 
 int cdwac_sigma(cdwac_ctx* ctx, int32_t n_omega, const double* omega, double* sigma, double* i_term,

@@ -44,9 +44,8 @@ struct Shared {
     float h2[64];
 };
 
-// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).
-__device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R,
-                            double* Ri = nullptr) {
+// Partial sum of I_n(omega) (Eq. In_term, times pi) over this thread's m.
+__device__ inline double integral_partial(const QpArgs& A, int s, double omega, const Shared& sh) {
     const int nf = A.n_freq;
     const double* W = A.w_im + (int64_t)s * A.n_mo * nf;
     double isum = 0.0;
@@ -58,6 +57,13 @@ __device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, do
         for (int k = 0; k < nf; ++k) acc += sh.weight[k] * wm[k] * (am / (am2 + sh.freq[k] * sh.freq[k]));
         isum += acc;
     }
+    return isum;
+}
+
+// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).
+__device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R,
+                            double* Ri = nullptr) {
+    const double isum = integral_partial(A, s, omega, sh);
     double rsum = 0.0, risum = 0.0;
     const int m0 = A.m0[s], m1 = A.m1[s], foff = A.fit_off[s];
     for (int m = m0 + threadIdx.x; m < m1; m += kQpThreads) {
@@ -117,9 +123,9 @@ __device__ float mlp_one(const float* __restrict__ th, const float* x, Shared& s
     return y;
 }
 
-__global__ __launch_bounds__(kQpThreads) void k_qp_solve(QpArgs A, QpOut* __restrict__ out) {
-    __shared__ Shared sh;
-    const int s = blockIdx.x;
+// Root of the QP equation for state s of the system A, written to *dst by
+// thread 0 (the whole workgroup evaluates Sigma together).
+__device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
     for (int k = threadIdx.x; k < A.n_freq; k += kQpThreads) {
         sh.freq[k] = A.freq[k];
         sh.weight[k] = A.weight[k];
@@ -255,8 +261,22 @@ __global__ __launch_bounds__(kQpThreads) void k_qp_solve(QpArgs A, QpOut* __rest
         o.residual = (flags & CDWAC_FLAG_NOROOT_DEV) ? nan("") : root - e_n - (A.sigx[s] + R - I) + vxc;
         o.n_evals = n_eval;
         o.flags = flags;
-        out[s] = o;
+        *dst = o;
     }
+}
+
+__global__ __launch_bounds__(kQpThreads) void k_qp_solve(QpArgs A, QpOut* __restrict__ out) {
+    __shared__ Shared sh;
+    qp_state(A, blockIdx.x, sh, out + blockIdx.x);
+}
+
+// One workgroup per (system, state) of a batch: map[b] = {system, state}.
+__global__ __launch_bounds__(kQpThreads) void k_qp_solve_batch(const QpArgs* __restrict__ args,
+                                                               const int2* __restrict__ map,
+                                                               QpOut* __restrict__ out) {
+    __shared__ Shared sh;
+    const int2 m = map[blockIdx.x];
+    qp_state(args[m.x], m.y, sh, out + blockIdx.x);
 }
 
 // sigma[s][k] = Re Sigma_n(omega[s][k]) (+ I and R terms).
@@ -308,6 +328,39 @@ __global__ __launch_bounds__(kQpThreads) void k_spectral_eval(QpArgs A, int n_om
     }
 }
 
+// Full contour deformation (Sec. 2.3, Eqs. Rn_term, In_term, cdselfe) for
+// state 0 of A at one omega: W evaluated directly at every residue.  Residue
+// j is orbital rm[j] with occupation factor rf[j]; its W^c_nm(|eps_m - omega|
+// + i eta) is column fit rm[j] (every m fitted) at near-real point j of w_re.
+// out = {Sigma, R_n, I_n}.
+__global__ __launch_bounds__(kQpThreads) void k_sigma_direct(QpArgs A, double omega, const double* __restrict__ w_re,
+                                                             int n_re, const int* __restrict__ rm,
+                                                             const double* __restrict__ rf, double* __restrict__ out) {
+    __shared__ Shared sh;
+    for (int k = threadIdx.x; k < A.n_freq; k += kQpThreads) {
+        sh.freq[k] = A.freq[k];
+        sh.weight[k] = A.weight[k];
+    }
+    __syncthreads();
+    const double I = block_sum(integral_partial(A, 0, omega, sh), sh.red) / kPi;
+    double rsum = 0.0;
+    for (int j = threadIdx.x; j < n_re; j += kQpThreads) {
+        const int f = A.fit_off[0] + (rm[j] - A.m0[0]);
+        rsum += rf[j] * w_re[((int64_t)f * n_re + j) * 2];
+    }
+    const double R = block_sum(rsum, sh.red);
+    if (threadIdx.x == 0) {
+        out[0] = A.sigx[0] + R - I;
+        out[1] = R;
+        out[2] = I;
+    }
+}
+
+void launch_sigma_direct(hipStream_t s, const QpArgs& a, double omega, const double* w_re, int n_re, const int* rm,
+                         const double* rf, double* out) {
+    hipLaunchKernelGGL(k_sigma_direct, dim3(1), dim3(kQpThreads), 0, s, a, omega, w_re, n_re, rm, rf, out);
+}
+
 int qp_max_freq() { return kMaxFreq; }
 
 void launch_spectral(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* spec, double* sre,
@@ -319,6 +372,11 @@ void launch_spectral(hipStream_t s, const QpArgs& a, int n_omega, const double* 
 
 void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out) {
     hipLaunchKernelGGL(k_qp_solve, dim3(a.n_states), dim3(kQpThreads), 0, s, a, out);
+}
+
+void launch_qp_batch(hipStream_t s, int n_blocks, const QpArgs* args, const int2* map, QpOut* out) {
+    if (n_blocks <= 0) return;
+    hipLaunchKernelGGL(k_qp_solve_batch, dim3(n_blocks), dim3(kQpThreads), 0, s, args, map, out);
 }
 
 void launch_sigma(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* sigma,

@@ -108,6 +108,9 @@ void launch_gather_refs(hipStream_t s, int n_fit, const int* fit_s, const int* f
 
 // k_qp.hip
 int qp_max_freq();
+void launch_sigma_direct(hipStream_t s, const QpArgs& a, double omega, const double* w_re, int n_re, const int* rm,
+                         const double* rf, double* out);
+void launch_qp_batch(hipStream_t s, int n_blocks, const QpArgs* args, const int2* map, QpOut* out);
 void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out);
 void launch_sigma(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* sigma,
                   double* iterm, double* rterm);

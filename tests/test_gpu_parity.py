@@ -204,6 +204,33 @@ def test_refined_setting_fp64(lib, which, n_freq, n_core, n_val):
         assert abs(out[n]["qp"] - r[0]) <= 1e-9 * abs(r[0]), (n, out[n]["qp"], r[0])
 
 
+@pytest.mark.parametrize("prec", ["f16", "f16x3"])
+def test_near_real_planes_on_the_fp64_path(lib, prec):
+    """near_real_f64: Pi at the near-real reference points on the FP64 path in
+    the 16-bit modes.  There W sits within eta_ref of RPA poles of ~10 Ha, so
+    a 16-bit Pi (relative error d) moves them by d * Omega / eta_ref of their
+    width: measured near-real W errors of up to 9e-5 (split) and 8e-3 (one
+    product) of the state's largest W.  With the option the W contraction's
+    rounding is all that is left (measured <= 4e-7): bar 1e-6, against the
+    FP64 path's tables; the imaginary-node tables keep the 16-bit mode's
+    accuracy.  QP energies within 1 meV of the oracle."""
+    case = cases.ragged()
+    s = case.system
+    run(lib, case, "p64")
+    wi64, wr64, _, (m0, m1) = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+    run(lib, case, prec, freq_rank_tol=1e-10, near_real_f64=True)
+    wi, wr, _, _ = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+    out = lib.cdwac_qp(s.n_states)
+    f = 0
+    for n in range(s.n_states):
+        nf = m1[n] - m0[n]
+        gmax = np.max(np.abs(wr64[f:f + nf]))
+        assert np.max(np.abs(wr[f:f + nf] - wr64[f:f + nf])) <= 1e-6 * gmax, n
+        f += nf
+    for n, r in enumerate(cases.oracle(case).solve_all()):
+        assert abs(out[n]["qp"] - r[0]) <= MEV, (n, out[n]["qp"], r[0])
+
+
 def test_default_setting_reduced_precision(lib):
     """CD-WAC(20, 20, 200) with Pi in one fp16 product, W in the fp16 split and
     skeleton imaginary nodes: within 1 meV of the oracle."""
@@ -217,6 +244,46 @@ def test_default_setting_reduced_precision(lib):
     out = lib.cdwac_qp(s.n_states)
     for n, r in enumerate(o.solve_all()):
         assert abs(out[n]["qp"] - r[0]) <= MEV, (n, out[n]["qp"], r[0])
+
+
+# ------------------------------------------------ full contour deformation
+
+@pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])
+def test_full_cd_sigma_matches_oracle(lib, which):
+    """cdwac_sigma_cd: W evaluated directly at every residue (full CD, the
+    O(N^5) reference) against the oracle's full CD, FP64 path.  Full CD has
+    no continuation, so the bar is the FP64 one, 1e-9 relative, at points
+    between the core and valence residues and next to the state's own KS
+    energy (where the own residue has weight 1/2 at omega = eps_n)."""
+    case = cases.ragged() if which == "ragged" else cases.workload(which)
+    s = case.system
+    full = R.FullCdOracle(s, case.freq, case.weight, case.lo, case.hi, eta=case.eta)
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, prec="p64")
+    for n in range(s.n_states):
+        e_n = s.eps[s.state_idx[n]]
+        for d in (-0.3, -0.05, 0.0, 0.1):
+            sig, r_term, i_term, nres = lib.cdwac_sigma_cd(sysc, prm, n, e_n + d)
+            ref = full.sigma(n, e_n + d)
+            assert nres > 0
+            assert abs(sig - ref) <= 1e-9 * abs(ref), (n, d, sig, ref)
+
+
+def test_full_cd_sigma_reduced_precision(lib):
+    """Full CD with Pi in the fp16 split and the near-real planes on the FP64
+    path: the residue term then carries only the W contraction's rounding."""
+    case = cases.ragged()
+    s = case.system
+    full = R.FullCdOracle(s, case.freq, case.weight, case.lo, case.hi, eta=case.eta)
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, prec="f16x3", near_real_f64=True)
+    e_n = s.eps[s.state_idx[0]]
+    for d in (-0.2, 0.05):
+        sig = lib.cdwac_sigma_cd(sysc, prm, 0, e_n + d)[0]
+        ref = full.sigma(0, e_n + d)
+        assert abs(sig - ref) <= 1e-6 * abs(ref), (d, sig, ref)
 
 
 # ------------------------------------------------------------------ Pade

@@ -9,7 +9,7 @@ from paper_2305_15955_amd import cdwac
 
 def test_header_declares_the_boundary():
     names = cdwac.header_functions()
-    for n in ("cdwac_ctx_create", "cdwac_prepare", "cdwac_qp", "cdwac_solve", "cdwac_sigma",
+    for n in ("cdwac_ctx_create", "cdwac_prepare", "cdwac_qp", "cdwac_solve", "cdwac_solve_batch", "cdwac_sigma",
               "cdwac_polarizability", "cdwac_pade_fit_eval", "cdwac_mlp_train"):
         assert n in names
 
@@ -32,8 +32,11 @@ def test_struct_layouts_match_header():
 
 def test_params_layout_matches_header():
     # n_freq(+pad), freq, weight, n_ref_im(+pad), ref_im_idx, n_ref_re(+pad), ref_re, eta_ref, eta,
-    # pade_tol, win_lo, win_hi, qp_tol, qp_maxit, prec, use_mlp_seed(+pad), mlp_accept, freq_rank_tol
-    assert ctypes.sizeof(cdwac.CdwacParams) == 8 + 16 + 8 + 8 + 8 + 8 + 3 * 8 + 2 * 8 + 8 + 3 * 4 + 4 + 2 * 8
+    # pade_tol, win_lo, win_hi, qp_tol, qp_maxit, prec, use_mlp_seed(+pad), mlp_accept, freq_rank_tol,
+    # fit_all, near_real_f64
+    assert ctypes.sizeof(cdwac.CdwacParams) == 8 + 16 + 8 + 8 + 8 + 8 + 3 * 8 + 2 * 8 + 8 + 3 * 4 + 4 + 2 * 8 + 8
+    assert cdwac.CdwacParams.fit_all.offset == ctypes.sizeof(cdwac.CdwacParams) - 8
+    assert cdwac.CdwacParams.near_real_f64.offset == ctypes.sizeof(cdwac.CdwacParams) - 4
 
 
 def test_freq_decomposition_interpolates_w_family():
