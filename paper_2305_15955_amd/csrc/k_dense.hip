@@ -197,13 +197,15 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 
 constexpr int GT = 256, GK = 32, KGR = GK / 8;
 constexpr int kGemmThreads = 512;
-constexpr int kGemmLds = 8192;                  // uint4 slots of the LDS ring (128 KiB)
-// uint4 slots of one operand per stage, of a stage, and the ring depth
+// uint4 slots of the LDS ring (128 KiB: 2 stages of 64 KiB with the split,
+// 4 stages of 32 KiB without it), of one operand per stage, of a stage, and
+// the ring depth
 template <bool SPLIT>
 struct Ring {
+    static constexpr int SLOTS = 8192;
     static constexpr int OP = (SPLIT ? 2 : 1) * KGR * GT;
     static constexpr int STAGE = 2 * OP;
-    static constexpr int NST = kGemmLds / STAGE;
+    static constexpr int NST = SLOTS / STAGE;
 };
 // 64-row-block loads per chunk: 2 operands x 2 planes x KGR k-groups x 4 row
 // blocks with the hi/lo split, the hi planes alone without it
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
                                                           const double* __restrict__ pi_unscale,
                                                           const int* __restrict__ idflag, double* __restrict__ E,
                                                           int npad) {
-    __shared__ uint4 lds[kGemmLds];
+    __shared__ uint4 lds[Ring<SPLIT>::SLOTS];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fb = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
@@ -358,8 +360,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
                                                          const int2* __restrict__ tiles, int n_tiles, int f0,
                                                          const double* __restrict__ w_unscale,
                                                          double* __restrict__ partial) {
-    __shared__ uint4 lds[kGemmLds];
-    __shared__ double red[4][GT];
+    __shared__ uint4 lds[Ring<SPLIT>::SLOTS];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fl = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
@@ -369,6 +370,9 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
     const int64_t bo = (int64_t)J * GT * npad;
     v16f acc[2][4];
     gemm_tile<ET, SPLIT>(lds, lh + lo, ll + lo, bh + bo, bl + bo, npad, acc);
+    // the column sums reuse the ring once every wave is done reading it
+    __syncthreads();
+    double (*red)[GT] = reinterpret_cast<double (*)[GT]>(lds);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double us = w_unscale[f0 + fl];
 #pragma unroll
