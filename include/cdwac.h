@@ -188,6 +188,30 @@ int cdwac_solve_batch(cdwac_ctx *ctx, int32_t n_sys, const cdwac_system *sys, co
 int cdwac_sigma(cdwac_ctx *ctx, int32_t n_omega, const double *omega, double *sigma,
                 double *i_term, double *r_term);
 
+/* Replaces the orbital energies of G in the self-energy (I_n and R_n of
+ * Eqs. In_term, Rn_term, the occupation factors of Eq. ffact and the Fermi
+ * level) while W and its continuation stay as prepared: the G of the
+ * eigenvalue-self-consistent schemes of Sec. 4.  The QP equation keeps the KS
+ * eps_n and v^xc_n.  eps_g: host [n_mo] (Ha).  eps_fermi: NaN selects the
+ * midpoint of eps_g[n_occ - 1] and eps_g[n_occ].  Needs a preparation with
+ * fit_all = 1 (moved energies can put any m's residue in the window).
+ * Holds until the next cdwac_prepare. */
+int cdwac_set_g_energies(cdwac_ctx *ctx, const double *eps_g, double eps_fermi);
+
+/* Eigenvalue self-consistency (Sec. 4, the evGW0 and evGW flavours):
+ * mode 0 (evGW0) prepares W once from the KS energies and iterates the QP
+ * equations with the QP energies in G; mode 1 (evGW) also rebuilds Pi, eps^-1,
+ * W and the fits from the QP energies every iteration.  The energies of the
+ * computed states (sys->state_idx) are updated after every iteration, the
+ * others keep their input values; a state without a root keeps its energy.
+ * Stops when no energy moves by more than tol (Ha) or after max_iter QP
+ * solves.  prm is used with fit_all = 1 and without the learned seed.
+ * eps_out: host [n_mo], the final energies; n_iter: host, the QP solves done;
+ * out: host [n_states], the last solve's results.  Returns CDWAC_WNOROOT if a
+ * state of the last solve has no root. */
+int cdwac_evgw(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm, int32_t mode,
+               int32_t max_iter, double tol, double *eps_out, int32_t *n_iter, cdwac_state_out *out);
+
 /* Sigma_n(omega) by full contour deformation (Sec. 2.3, Eqs. Rn_term,
  * In_term, cdselfe): W^c_nm evaluated directly at every residue
  * |eps_m - omega| + i*eta with f_m(omega) != 0 (Eq. ffact), i.e. one complex

@@ -364,9 +364,15 @@ class CdwacOracle:
 
     def __init__(self, system, freq, weight, ref_im_idx, ref_re, win_lo, win_hi,
                  eta: float = 1e-3, eta_ref: float = 1e-3, pade_tol: float = 1e-9,
-                 vxc=None, eps_fermi: Optional[float] = None):
+                 vxc=None, eps_fermi: Optional[float] = None, fit_all: bool = False,
+                 eps_qp=None):
         self.sys = system
         self.eps = np.asarray(system.eps, np.float64)
+        # energies of G in the self-energy (set_g_energies replaces them) and
+        # eps_n of the QP equation (the KS energies)
+        self.eps_g = self.eps
+        self.eps_qp = self.eps if eps_qp is None else np.asarray(eps_qp, np.float64)
+        self.fit_all = fit_all
         self.freq = np.asarray(freq, np.float64)
         self.weight = np.asarray(weight, np.float64)
         self.ref_im_idx = np.asarray(ref_im_idx, np.int64)
@@ -388,13 +394,22 @@ class CdwacOracle:
             np.zeros((system.n_states, system.n_mo, 0), np.complex128)
         self.fits = []
         for s in range(system.n_states):
-            m0, m1 = fit_range(self.eps, system.n_occ, self.win_lo[s] - QP_Z_STEP,
-                               self.win_hi[s] + QP_Z_STEP)
+            m0, m1 = (0, system.n_mo) if fit_all else fit_range(
+                self.eps, system.n_occ, self.win_lo[s] - QP_Z_STEP, self.win_hi[s] + QP_Z_STEP)
             models = {}
             for m in range(m0, m1):
                 u, w = self.reference_data(s, m)
                 models[m] = thiele_greedy(u, w, self.pade_tol)
             self.fits.append(models)
+
+    def set_g_energies(self, eps_g, eps_fermi: Optional[float] = None):
+        """Orbital energies of G in I_n, R_n and Eq. (ffact); W and its models
+        stay (the G of the eigenvalue-self-consistent schemes, Sec. 4).  Every
+        m needs a model, so the oracle must be built with fit_all."""
+        if not self.fit_all:
+            raise ValueError("set_g_energies needs an oracle built with fit_all=True")
+        self.eps_g = np.asarray(eps_g, np.float64)
+        self.eps_f = fermi_level(self.eps_g, self.sys.n_occ) if eps_fermi is None else eps_fermi
 
     def reference_data(self, s: int, m: int):
         """(u_j, W_j) over F_wac = re-used imaginary nodes + near-real points."""
@@ -410,8 +425,8 @@ class CdwacOracle:
 
     def sigma(self, s: int, omega: float) -> float:
         """Re Sigma_n(omega) = Sigma^x + Re R - I (Eq. cdselfe), CD-WAC."""
-        i_term = integral_term(omega, self.eps, self.w_im[s], self.freq, self.weight)
-        r_term = residue_term(omega, self.eps, self.eps_f, self.eta,
+        i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
+        r_term = residue_term(omega, self.eps_g, self.eps_f, self.eta,
                               lambda m, z: self.w_model(s, m, z))
         return self.sigma_x[s] + r_term - i_term
 
@@ -420,19 +435,19 @@ class CdwacOracle:
 
     def sigma_complex(self, s: int, omega: float) -> complex:
         """Sigma^x + R - I with the complex residue term."""
-        i_term = integral_term(omega, self.eps, self.w_im[s], self.freq, self.weight)
-        r_term = residue_term_complex(omega, self.eps, self.eps_f, self.eta,
+        i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
+        r_term = residue_term_complex(omega, self.eps_g, self.eps_f, self.eta,
                                       lambda m, z: self.w_model(s, m, z))
         return self.sigma_x[s] + r_term - i_term
 
     def spectral(self, s: int, omega: float, vxc: Optional[float] = None) -> float:
         n = int(self.sys.state_idx[s])
         v = float(self.vxc[s]) if vxc is None else vxc
-        return spectral_function(omega, float(self.eps[n]), self.sigma_complex(s, omega), v)
+        return spectral_function(omega, float(self.eps_qp[n]), self.sigma_complex(s, omega), v)
 
     def solve(self, s: int, tol: float = 1e-10, maxit: int = 100):
         n = int(self.sys.state_idx[s])
-        e_n = float(self.eps[n])
+        e_n = float(self.eps_qp[n])
         vxc = float(self.vxc[s])
         return qp_solve(lambda x: x - e_n - self.sigma(s, x) + vxc, e_n,
                         float(self.win_lo[s]), float(self.win_hi[s]), tol, maxit)
@@ -450,10 +465,10 @@ class FullCdOracle(CdwacOracle):
     """
 
     def __init__(self, system, freq, weight, win_lo, win_hi, eta: float = 1e-3,
-                 vxc=None, eps_fermi: Optional[float] = None):
+                 vxc=None, eps_fermi: Optional[float] = None, eps_qp=None):
         super().__init__(system, freq, weight, np.zeros(0, np.int64), np.zeros(0),
                          win_lo, win_hi, eta=eta, eta_ref=eta, pade_tol=0.0,
-                         vxc=vxc, eps_fermi=eps_fermi)
+                         vxc=vxc, eps_fermi=eps_fermi, fit_all=True, eps_qp=eps_qp)
         self._cache = {}
 
     def w_direct(self, s: int, m: int, z: complex) -> complex:
@@ -465,10 +480,50 @@ class FullCdOracle(CdwacOracle):
         return complex(self._cache[key][m])
 
     def sigma(self, s: int, omega: float) -> float:
-        i_term = integral_term(omega, self.eps, self.w_im[s], self.freq, self.weight)
-        r_term = residue_term(omega, self.eps, self.eps_f, self.eta,
+        i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
+        r_term = residue_term(omega, self.eps_g, self.eps_f, self.eta,
                               lambda m, z: self.w_direct(s, m, z))
         return self.sigma_x[s] + r_term - i_term
+
+
+# ---------------------------------------------------------------------------
+# Eigenvalue self-consistency (Sec. 4: evGW0 and evGW)
+# ---------------------------------------------------------------------------
+
+def evgw(system, make, mode: str, max_iter: int = 20, tol: float = 1e-8):
+    """Iterates the QP equations with the QP energies fed back.
+
+    ``make(system_w, eps_qp)`` builds a self-energy object (an oracle with
+    fit_all) whose W comes from ``system_w.eps`` and whose QP equation uses
+    ``eps_qp`` (the KS energies).  evGW0 builds it once from the KS energies
+    and replaces only the energies of G; evGW rebuilds it (Pi, Lambda, W, the
+    fits) from the current energies every iteration.  The energies of the
+    computed states are replaced after each solve (a state without a root
+    keeps its energy); the others keep their input values.  Stops once no
+    energy moves by more than ``tol`` or after ``max_iter`` solves.
+    Returns (energies, solves, results of the last solve).
+    """
+    import dataclasses
+    ks = np.asarray(system.eps, np.float64).copy()
+    cur = ks.copy()
+    o = None
+    it = 0
+    res = None
+    for it in range(1, max_iter + 1):
+        if mode == "evgw" or o is None:
+            sys_w = dataclasses.replace(system, eps=cur.copy()) if mode == "evgw" else system
+            o = make(sys_w, ks)
+        o.set_g_energies(cur)
+        res = o.solve_all()
+        nxt = cur.copy()
+        for j, r in enumerate(res):
+            if not r[3] & FLAG_NOROOT:
+                nxt[int(system.state_idx[j])] = r[0]
+        delta = float(np.max(np.abs(nxt - cur)))
+        cur = nxt
+        if delta < tol:
+            break
+    return cur, it, res
 
 
 # ---------------------------------------------------------------------------

@@ -73,6 +73,9 @@ _SIGNATURES = {
     "cdwac_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "cdwac_prepare": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams)]),
     "cdwac_qp": (ctypes.c_int, [_vp, _f64p, ctypes.POINTER(CdwacStateOut)]),
+    "cdwac_set_g_energies": (ctypes.c_int, [_vp, _f64p, ctypes.c_double]),
+    "cdwac_evgw": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams), ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_double, _f64p, _i32p, ctypes.POINTER(CdwacStateOut)]),
     "cdwac_sigma_cd": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams),
                                       ctypes.c_int32, ctypes.c_double, _f64p, _i32p]),
     "cdwac_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(CdwacSystem),
@@ -305,6 +308,23 @@ class Cdwac:
             res.append(flat[k:k + c])
             k += c
         return res
+
+    def cdwac_set_g_energies(self, eps_g, eps_fermi=None):
+        e = np.ascontiguousarray(eps_g, np.float64)
+        _check(self.ctx, self.lib.cdwac_set_g_energies(self.ctx, _np_ptr(e, ctypes.c_double),
+                                                       math.nan if eps_fermi is None else float(eps_fermi)))
+
+    def cdwac_evgw(self, sysc, prm, mode: str = "evgw0", max_iter: int = 20, tol: float = 1e-8):
+        """mode 'evgw0' (W from the KS energies) or 'evgw' (W rebuilt) ->
+        (final energies [n_mo], QP solves done, last solve's state results)."""
+        eps = np.zeros(sysc.n_mo, np.float64)
+        nit = ctypes.c_int32(0)
+        out = (CdwacStateOut * sysc.n_states)()
+        rc = self.lib.cdwac_evgw(self.ctx, ctypes.byref(sysc), ctypes.byref(prm),
+                                 {"evgw0": 0, "evgw": 1}[mode], int(max_iter), float(tol),
+                                 _np_ptr(eps, ctypes.c_double), ctypes.byref(nit), out)
+        _check(self.ctx, rc, allow_warn=True)
+        return eps, int(nit.value), _outs(out)
 
     def cdwac_sigma_cd(self, sysc, prm, state: int, omega: float):
         """Full-CD Sigma_n(omega) -> (Sigma, R_n, I_n, residue count)."""

@@ -39,7 +39,7 @@ struct Plan {
     bool nr64;    // 16-bit mode with the near-real planes of Pi on the FP64 path
     int64_t K, kpad;
     // persistent regions
-    Region eps, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
+    Region eps, eps_g, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
         fit_m, w_im, w_re, coef, node, nterm, qpout, err;
     // transient regions (prepare only)
     Region zr, zi, part, idflag, amax, sf, cw, cw64, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
@@ -62,6 +62,7 @@ struct HostState {
     int qp_maxit = 100, use_mlp = 0;
     double mlp_accept = 0.0;
     bool vxc_is_sigx = false;
+    bool fit_all = false;
     // imaginary nodes with a plane (ascending), the others, and the
     // interpolation of W at the others: W_rest[r] = sum_j T[r][j] W_node[j]
     std::vector<int> node, rest;
@@ -335,8 +336,11 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     std::vector<double> T;
     double om_lo = 0.0, om_hi = 0.0;
     if (allow_id && P.prec != CDWAC_P64 && p->freq_rank_tol > 0.0 && P.n_freq >= 4) {
-        om_lo = s->eps[s->n_occ] - s->eps[s->n_occ - 1];
-        om_hi = kOmegaHiFactor * (s->eps[s->n_mo - 1] - s->eps[0]);
+        // transition energies span [min virt - max occ, max - min] (the
+        // energies need not be sorted inside a block, e.g. QP energies of evGW)
+        const double* e = s->eps;
+        om_lo = *std::min_element(e + s->n_occ, e + s->n_mo) - *std::max_element(e, e + s->n_occ);
+        om_hi = kOmegaHiFactor * (*std::max_element(e, e + s->n_mo) - *std::min_element(e, e + s->n_mo));
         FreqId fid;
         if (freq_id(p->freq, P.n_freq, om_lo, om_hi, p->freq_rank_tol, fid)) {
             node = fid.skel;
@@ -389,6 +393,7 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     const int64_t blk = (int64_t)kNb * kNb;
     // persistent
     add(P, P.eps, sizeof(double) * P.n_mo);
+    add(P, P.eps_g, sizeof(double) * P.n_mo);
     add(P, P.freq, sizeof(double) * P.n_freq);
     add(P, P.weight, sizeof(double) * P.n_freq);
     add(P, P.ref_re, sizeof(double) * std::max(P.n_re, 1));
@@ -565,7 +570,8 @@ QpArgs qp_args(cdwac_ctx* c) {
     a.n_states = P.S;
     a.n_freq = P.n_freq;
     a.n_pts = P.n_pts;
-    a.eps = at<double>(c, P.eps);
+    a.eps = at<double>(c, P.eps_g);
+    a.eps_n = at<double>(c, P.eps);
     a.freq = at<double>(c, P.freq);
     a.weight = at<double>(c, P.weight);
     a.w_im = at<double>(c, P.w_im);
@@ -689,6 +695,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     hs.use_mlp = prm->use_mlp_seed;
     hs.mlp_accept = prm->mlp_accept;
     hs.vxc_is_sigx = sys->vxc == nullptr;
+    hs.fit_all = prm->fit_all != 0;
     if (sys->vxc) hs.vxc.assign(sys->vxc, sys->vxc + P.S);
 
     // weight vectors: imaginary nodes, then (Re, Im) of every near-real point
@@ -712,6 +719,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     for (int f = 0; f < P.n_fit; ++f) rowsel[f] = hs.fit_s[f] * P.n_mo + hs.fit_m[f];
 
     TRY(upload(ctx, at<double>(ctx, P.eps), sys->eps, P.n_mo));
+    TRY(upload(ctx, at<double>(ctx, P.eps_g), sys->eps, P.n_mo));
     TRY(upload(ctx, at<double>(ctx, P.freq), prm->freq, P.n_freq));
     TRY(upload(ctx, at<double>(ctx, P.weight), prm->weight, P.n_freq));
     if (P.n_re) TRY(upload(ctx, at<double>(ctx, P.ref_re), prm->ref_re, P.n_re));
@@ -907,7 +915,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
         // Omega_max^2 <= D_max^2 + lambda_max(A A^T) and A A^T <= (w_max^2 + D_max^2) (-Pi(i w_max)),
         // lambda_max(-Pi) <= its largest absolute row sum
         const double g = *std::max_element(rows.begin(), rows.end());
-        const double dmax = sys->eps[P.n_mo - 1] - sys->eps[0];
+        const double dmax = *std::max_element(sys->eps, sys->eps + P.n_mo) - *std::min_element(sys->eps, sys->eps + P.n_mo);
         const double wmax = *std::max_element(prm->freq, prm->freq + P.n_freq);
         const double om_bound = std::sqrt(dmax * dmax + (wmax * wmax + dmax * dmax) * g);
         if (!(om_bound <= hs.omega_hi)) return prepare_impl(ctx, sys, prm, false, sink);
@@ -1077,6 +1085,7 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
         TRY(copy_d2d(ctx, b.fit_off, at<int>(ctx, P.fit_off), sizeof(int) * P.S));
         QpArgs a = qp_args(ctx);
         a.eps = (const double*)(base + b.eps);
+        a.eps_n = a.eps;
         a.freq = (const double*)(base + b.freq);
         a.weight = (const double*)(base + b.weight);
         a.w_im = (const double*)(base + b.w_im);
@@ -1126,6 +1135,73 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
     HIPCK(hipStreamSynchronize(st));
     TRY(seg_collect(ctx));
     for (int j = 0; j < s_tot; ++j)
+        if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
+    return CDWAC_OK;
+}
+
+int cdwac_set_g_energies(cdwac_ctx* ctx, const double* eps_g, double eps_fermi) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_set_g_energies called before cdwac_prepare");
+    if (!ctx->hs.fit_all)
+        return fail(ctx, CDWAC_EINVAL, "G energies need a preparation with fit_all = 1 (a model for every m)");
+    const Plan& P = ctx->plan;
+    if (!eps_g || !finite_all(eps_g, P.n_mo)) return fail(ctx, CDWAC_EINVAL, "eps_g must hold n_mo finite values");
+    if (!std::isnan(eps_fermi) && !std::isfinite(eps_fermi)) return fail(ctx, CDWAC_EINVAL, "eps_fermi not finite");
+    HIPCK(hipSetDevice(ctx->device));
+    TRY(upload(ctx, at<double>(ctx, P.eps_g), eps_g, P.n_mo));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    ctx->hs.eps_f = std::isnan(eps_fermi) ? 0.5 * (eps_g[P.n_occ - 1] + eps_g[P.n_occ]) : eps_fermi;
+    return CDWAC_OK;
+}
+
+int cdwac_evgw(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* prm, int32_t mode, int32_t max_iter,
+               double tol, double* eps_out, int32_t* n_iter, cdwac_state_out* out) {
+    if (!ctx) return CDWAC_EINVAL;
+    ctx->prepared = false;
+    TRY(validate_system(ctx, sys));
+    TRY(validate_params(ctx, sys, prm));
+    if (mode != 0 && mode != 1) return fail(ctx, CDWAC_EINVAL, "mode must be 0 (evGW0) or 1 (evGW)");
+    if (max_iter < 1 || !(tol > 0.0)) return fail(ctx, CDWAC_EINVAL, "max_iter >= 1 and tol > 0 required");
+    if (!eps_out || !out) return fail(ctx, CDWAC_EINVAL, "eps_out / out is NULL");
+    const int n_mo = sys->n_mo, n_occ = sys->n_occ, S = sys->n_states;
+    std::vector<double> ks(sys->eps, sys->eps + n_mo), cur = ks;
+    cdwac_params p1 = *prm;
+    p1.fit_all = 1;                   // G energies move: every m needs a model
+    p1.use_mlp_seed = 0;
+    cdwac_system s1 = *sys;
+    s1.eps_fermi = NAN;               // the Fermi level follows the G energies
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        if (mode == 1 || it == 0) {
+            // evGW: Pi and W from the current energies (eps_ia = cur_a - cur_i > 0 checked)
+            double occ_max = *std::max_element(cur.begin(), cur.begin() + n_occ);
+            double virt_min = *std::min_element(cur.begin() + n_occ, cur.end());
+            if (!(occ_max < virt_min))
+                return fail(ctx, CDWAC_EINVAL, "iteration %d: an occupied QP energy rose above a virtual one", it);
+            s1.eps = cur.data();
+            TRY(prepare_impl(ctx, &s1, &p1, true));
+            const Plan& P = ctx->plan;
+            TRY(upload(ctx, at<double>(ctx, P.eps), ks.data(), n_mo));   // eps_n of the QP equation stays KS
+        }
+        TRY(cdwac_set_g_energies(ctx, cur.data(), NAN));
+        const int rc = cdwac_qp(ctx, nullptr, out);
+        if (rc != CDWAC_OK && rc != CDWAC_WNOROOT) return rc;
+        double delta = 0.0;
+        std::vector<double> nxt = cur;
+        for (int j = 0; j < S; ++j)
+            if (!(out[j].flags & CDWAC_FLAG_NOROOT)) {
+                nxt[sys->state_idx[j]] = out[j].qp;
+                delta = std::max(delta, std::fabs(out[j].qp - cur[sys->state_idx[j]]));
+            }
+        cur = nxt;
+        if (delta < tol) {
+            ++it;
+            break;
+        }
+    }
+    std::copy(cur.begin(), cur.end(), eps_out);
+    if (n_iter) *n_iter = it;
+    for (int j = 0; j < S; ++j)
         if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
     return CDWAC_OK;
 }

@@ -131,7 +131,7 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
         sh.weight[k] = A.weight[k];
     }
     __syncthreads();
-    const double e_n = A.eps[A.state_idx[s]];
+    const double e_n = A.eps_n[A.state_idx[s]];
     const double vxc = A.vxc[s];
     const double lo = A.win_lo[s], hi = A.win_hi[s];
     int n_eval = 0, flags = 0;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kQpThreads) void k_spectral_eval(QpArgs A, int n_om
     sigma_terms(A, s, w, sh, I, R, &Ri);
     if (threadIdx.x == 0) {
         const double re = A.sigx[s] + R - I;
-        const double dr = w - A.eps[A.state_idx[s]] - re + A.vxc[s], di = -Ri;
+        const double dr = w - A.eps_n[A.state_idx[s]] - re + A.vxc[s], di = -Ri;
         spec[o] = fabs(di) / (dr * dr + di * di) / kPi;
         if (sre) sre[o] = re;
         if (sim) sim[o] = Ri;

@@ -15,7 +15,8 @@ constexpr int CDWAC_FLAG_MLP_ACCEPTED_DEV = 4;
 // Everything the self-energy / root kernels read (device pointers unless noted).
 struct QpArgs {
     int n_mo, n_states, n_freq, n_pts;
-    const double* eps;
+    const double* eps;       // [n_mo] energies of G (the KS ones unless replaced)
+    const double* eps_n;     // [n_mo] KS energies: eps_n of the QP equation
     const double* freq;
     const double* weight;
     const double* w_im;      // [S][n_mo][n_freq]

@@ -248,6 +248,64 @@ def test_default_setting_reduced_precision(lib):
         assert abs(out[n]["qp"] - r[0]) <= MEV, (n, out[n]["qp"], r[0])
 
 
+# ------------------------------------------- eigenvalue self-consistency
+
+def g_shifted(s, seed=5):
+    """G energies for the tests: the computed cores moved by +1 eV (their G
+    poles stay clear of the QP roots ~3 eV above), the rest by up to 0.5 eV."""
+    rng = np.random.default_rng(seed)
+    e = s.eps + rng.uniform(-0.5, 0.5, s.n_mo) / synth.HARTREE_EV
+    e[s.state_idx] = s.eps[s.state_idx] + 1.0 / synth.HARTREE_EV
+    return e
+
+
+@pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])
+def test_g_energies_sigma_and_qp_fp64(lib, which):
+    """cdwac_set_g_energies: Sigma with G's energies moved and W as prepared
+    (the G of evGW0, Sec. 4) against the oracle, FP64 path: Sigma and the QP
+    energies (with the KS eps_n in the QP equation) to 1e-9 relative."""
+    case = cases.ragged() if which == "ragged" else cases.workload(which)
+    s = case.system
+    eg = g_shifted(s)
+    o = R.CdwacOracle(s, case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                      eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, fit_all=True)
+    o.set_g_energies(eg)
+    run(lib, case, "p64", fit_all=True)
+    lib.cdwac_set_g_energies(eg)
+    oms = np.array([[s.eps[s.state_idx[n]] + d for d in (-0.05, 0.05, 0.12)] for n in range(s.n_states)])
+    sig = lib.cdwac_sigma(oms)
+    for n in range(s.n_states):
+        for k in range(oms.shape[1]):
+            ref = o.sigma(n, oms[n, k])
+            assert abs(sig[n, k] - ref) <= 1e-9 * abs(ref), (n, k, sig[n, k], ref)
+    out = lib.cdwac_qp(s.n_states)
+    for n, r in enumerate(o.solve_all()):
+        assert out[n]["flags"] == r[3]
+        assert abs(out[n]["qp"] - r[0]) <= 1e-9 * abs(r[0]), (n, out[n]["qp"], r[0])
+
+
+@pytest.mark.parametrize("mode", ["evgw0", "evgw"])
+def test_evgw_two_solves_fp64(lib, mode):
+    """cdwac_evgw against the oracle's loop for two QP solves (the second one
+    with the first one's QP energies in G, and in W for evGW), FP64 path, to
+    1e-9 relative.  Longer runs are not compared: with the core's own G pole
+    at its QP energy the CD self-energy jumps there and the fixed-point
+    iteration of a core state wanders (Z drops to ~0.2)."""
+    case = cases.workload("fp64_1core_nmo60")
+    s = case.system
+    make = lambda sw, ks: R.CdwacOracle(sw, case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                        eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol,
+                                        fit_all=True, eps_qp=ks)
+    e_ref, it_ref, res = R.evgw(s, make, mode, max_iter=2, tol=1e-14)
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, prec="p64")
+    e, it, out = lib.cdwac_evgw(sysc, prm, mode, max_iter=2, tol=1e-14)
+    assert it == it_ref == 2
+    np.testing.assert_allclose(e, e_ref, rtol=1e-9, atol=0)
+    assert [x["flags"] for x in out] == [r[3] for r in res]
+
+
 # ------------------------------------------------ full contour deformation
 
 @pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])

@@ -253,6 +253,68 @@ def test_full_cd_equals_pole_sum_cfg1():
                                                    rel=1e-6, abs=1e-9)
 
 
+def test_moved_g_energies_full_cd_equals_pole_sum():
+    """G with other orbital energies than W (the G of the eigenvalue-self-
+    consistent schemes, Sec. 4): full CD with W from the KS energies and the
+    occupation factors, residues and integral term from shifted energies
+    reproduces the pole form of Eq. (sigma_pole) with W's poles and couplings
+    from the KS energies and G's poles at the shifted ones.  Shifts: the core
+    by +1.0 eV (its G pole stays clear of the QP root near -287.2 eV, where
+    the own residue would switch), valence and virtual levels by seeded
+    amounts up to 0.6 eV."""
+    import dataclasses
+    s, freq, wts, _, _, lo, hi = cfg1_inputs()
+    freq, wts = grids.gauss_legendre_imag(100)
+    rng = np.random.default_rng(3)
+    eps_g = s.eps + rng.uniform(-0.6, 0.6, s.n_mo) / synth.HARTREE_EV
+    eps_g[0] = s.eps[0] + 1.0 / synth.HARTREE_EV
+    fc = R.FullCdOracle(s, freq, wts, lo, hi, eta=1e-5)
+    fc.set_g_energies(eps_g)
+    poles = R.rpa_poles(s)
+    sys_g = dataclasses.replace(s, eps=eps_g)
+    for om_ev in (-300.0, -292.0, -283.0, -275.0):
+        om = om_ev / synth.HARTREE_EV
+        assert fc.sigma_c(0, om) == pytest.approx(R.sigma_c_poles(sys_g, 0, om, poles),
+                                                   rel=1e-6, abs=1e-9)
+    # the QP equation keeps the KS eps_n: G energies alone do not move eps_n
+    fc2 = R.FullCdOracle(s, freq, wts, lo, hi, eta=1e-5, eps_qp=s.eps)
+    fc2.set_g_energies(eps_g)
+    n_res = fc2.solve(0)
+    f = lambda w: w - s.eps[0] - R.sigma_c_poles(sys_g, 0, w, poles)
+    assert n_res[0] == pytest.approx(R.qp_solve(f, s.eps[0], lo[0], hi[0])[0], abs=1e-7)
+
+
+def test_evgw_loop_on_the_pole_form():
+    """The eigenvalue loop feeds each solve's QP energies back into G (evGW0)
+    or into G and W (evGW).  On a single transition with W and G from the pole
+    form, evGW0 after two solves equals two hand-iterated solves."""
+    import dataclasses
+    s = one_transition()
+    freq, wts = grids.gauss_legendre_imag(200)
+    lo, hi = np.array([-12.0]), np.array([-8.0])
+    make = lambda sw, ks: R.FullCdOracle(sw, freq, wts, lo, hi, eta=1e-7, eps_qp=ks)
+    e2, it, _ = R.evgw(s, make, "evgw0", max_iter=2, tol=1e-14)
+    assert it == 2
+    poles = R.rpa_poles(s)
+    cur = s.eps.copy()
+    for _ in range(2):
+        sg = dataclasses.replace(s, eps=cur.copy())
+        f = lambda w: w - s.eps[0] - R.sigma_c_poles(sg, 0, w, poles)
+        cur = cur.copy()
+        cur[0] = R.qp_solve(f, s.eps[0], lo[0], hi[0])[0]
+    assert e2[0] == pytest.approx(cur[0], abs=1e-7)
+    assert e2[1] == s.eps[1]                   # not a computed state: keeps its energy
+    # evGW: W from the updated energies as well
+    e2w, _, _ = R.evgw(s, make, "evgw", max_iter=2, tol=1e-14)
+    cur = s.eps.copy()
+    for _ in range(2):
+        sg = dataclasses.replace(s, eps=cur.copy())
+        f = lambda w: w - s.eps[0] - R.sigma_c_poles(sg, 0, w, R.rpa_poles(sg))
+        cur = cur.copy()
+        cur[0] = R.qp_solve(f, s.eps[0], lo[0], hi[0])[0]
+    assert e2w[0] == pytest.approx(cur[0], abs=1e-7)
+
+
 def test_cdwac_within_5mev_of_full_cd_and_converges_with_m():
     errs = {}
     for n_pade in (8, 16, 24):
