@@ -146,7 +146,10 @@ def test_uneven_batch_48_systems(lib):
                 c.system.o_nm = None
             cs.append(c)
     print("batch staged on the device", flush=True)
+    import time
+    t = time.perf_counter()
     res = lib.cdwac_solve_batch(systems, params)
+    print(f"cdwac_solve_batch: 48 systems in {time.perf_counter() - t:.2f} s", flush=True)
     n_states = sum(c.system.n_states for c in cs)
     assert sum(len(r) for r in res) == n_states == sum(sp["n_core"] for sp in specs)
     print("states", n_states, "no root:", sum(bool(x["flags"] & R.FLAG_NOROOT) for r in res for x in r))

@@ -306,6 +306,31 @@ def test_evgw_two_solves_fp64(lib, mode):
     assert [x["flags"] for x in out] == [r[3] for r in res]
 
 
+def test_new_entry_points_reject_bad_arguments(lib):
+    """Status codes of the batch, G-energy, evGW and full-CD entry points
+    (checked before any launch)."""
+    cd = cdwac_mod()
+    case = cases.workload("fp64_1core_nmo60")
+    s = case.system
+    sysc, prm, keep = run(lib, case, "p64")            # prepared without fit_all
+    with pytest.raises(cd.CdwacError) as e:
+        lib.cdwac_set_g_energies(s.eps)
+    assert e.value.code == cd.CDWAC_EINVAL
+    with pytest.raises(cd.CdwacError) as e:
+        lib.cdwac_evgw(sysc, prm, "evgw0", max_iter=0)
+    assert e.value.code == cd.CDWAC_EINVAL
+    with pytest.raises(cd.CdwacError) as e:
+        lib.cdwac_sigma_cd(sysc, prm, 3, float(s.eps[0]))
+    assert e.value.code == cd.CDWAC_EINVAL
+    with pytest.raises(cd.CdwacError) as e:
+        lib.cdwac_sigma_cd(sysc, prm, 0, float("nan"))
+    assert e.value.code == cd.CDWAC_EINVAL
+    prm.near_real_f64 = 2
+    with pytest.raises(cd.CdwacError) as e:
+        lib.cdwac_prepare(sysc, prm)
+    assert e.value.code == cd.CDWAC_EINVAL
+
+
 # ------------------------------------------------ full contour deformation
 
 @pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])
