@@ -294,37 +294,42 @@ __device__ inline void lower_tile32(int t, int& I, int& J) {
 // Lambda = -E - delta_f I after the sweep (E holds -eps^{-1} in its lower
 // triangle; delta_f = 0 for the imaginary plane of a complex eps), mirrored in
 // place to a full symmetric FP64 matrix; max|Lambda_f| into lmax[f] if given.
-__global__ void k_finalize_lambda(double* __restrict__ E, int npad, const int* __restrict__ idflag,
-                                  uint32_t* __restrict__ lmax) {
-    __shared__ double tile[32][33];
-    const int nt = npad / 32, T = nt * (nt + 1) / 2;
+// One 64 x 64 lower tile per workgroup: a wave reads or writes 512-byte row
+// segments, and the tile goes through LDS for its mirror image.
+__global__ __launch_bounds__(256) void k_finalize_lambda(double* __restrict__ E, int npad,
+                                                         const int* __restrict__ idflag,
+                                                         uint32_t* __restrict__ lmax) {
+    __shared__ double tile[64][65];
+    const int nt = npad / 64, T = nt * (nt + 1) / 2;
     const int f = blockIdx.x / T;
     int I, J;
     lower_tile32(blockIdx.x % T, I, J);
     double* Ef = E + (int64_t)f * npad * npad;
     const double id = idflag[f] ? 1.0 : 0.0;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     double m = 0.0;
-    for (int yy = ty; yy < 32; yy += 8) {
-        int P = I * 32 + yy, Q = J * 32 + tx;
-        double v = (I == J && Q > P) ? 0.0 : Ef[(int64_t)P * npad + Q];
-        double l = -v - (P == Q ? id : 0.0);
+#pragma unroll 4
+    for (int yy = ty; yy < 64; yy += 4) {
+        const int P = I * 64 + yy, Q = J * 64 + tx;
+        const double v = (I == J && Q > P) ? 0.0 : Ef[(int64_t)P * npad + Q];
+        const double l = -v - (P == Q ? id : 0.0);
         tile[yy][tx] = l;
         m = fmax(m, fabs(l));
     }
     __syncthreads();
     if (I == J) {
-        for (int yy = ty; yy < 32; yy += 8)
+        for (int yy = ty; yy < 64; yy += 4)
             if (tx > yy) tile[yy][tx] = tile[tx][yy];
         __syncthreads();
     }
-    for (int yy = ty; yy < 32; yy += 8) {
-        Ef[(int64_t)(I * 32 + yy) * npad + J * 32 + tx] = tile[yy][tx];
-        if (I != J) Ef[(int64_t)(J * 32 + yy) * npad + I * 32 + tx] = tile[tx][yy];
+#pragma unroll 4
+    for (int yy = ty; yy < 64; yy += 4) {
+        Ef[(int64_t)(I * 64 + yy) * npad + J * 64 + tx] = tile[yy][tx];
+        if (I != J) Ef[(int64_t)(J * 64 + yy) * npad + I * 64 + tx] = tile[tx][yy];
     }
     if (lmax) {
         m = wave_max(m);
-        if ((threadIdx.x & 63) == 0) atomic_absmax(lmax + f, m);
+        if (tx == 0) atomic_absmax(lmax + f, m);
     }
 }
 
@@ -480,7 +485,7 @@ void launch_exchange(hipStream_t s, const double* onm, int S, int N, int n_mo, i
 }
 
 void launch_finalize_lambda(hipStream_t s, double* E, int npad, int n_f, const int* idflag, uint32_t* lmax) {
-    int nt = npad / 32, T = nt * (nt + 1) / 2;
+    int nt = npad / 64, T = nt * (nt + 1) / 2;
     hipLaunchKernelGGL(k_finalize_lambda, dim3(T * n_f), dim3(256), 0, s, E, npad, idflag, lmax);
 }
 
