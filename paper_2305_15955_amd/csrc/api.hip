@@ -91,6 +91,10 @@ struct cdwac_ctx {
     // MLP scratch
     void* mlp_scratch = nullptr;
     size_t mlp_scratch_bytes = 0;
+    // second stream (default priority) for the complex-plane sweep, and the
+    // events that fork it from and join it to the context's stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // tables of a batch of systems (cdwac_solve_batch)
     void* batch = nullptr;
     size_t batch_bytes = 0;
@@ -614,7 +618,13 @@ int cdwac_ctx_create(cdwac_ctx** out, int device, void* hip_stream) {
     cdwac_ctx* ctx = new cdwac_ctx();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
-    if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->mlp_theta, sizeof(float) * kMlpParams) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->mlp_theta, sizeof(float) * kMlpParams) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess) {
+        if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
+        if (ctx->side) (void)hipStreamDestroy(ctx->side);
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
         delete ctx;
         return CDWAC_EHIP;
     }
@@ -631,6 +641,9 @@ void cdwac_ctx_destroy(cdwac_ctx* ctx) {
     if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
     if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
     if (ctx->batch) (void)hipFree(ctx->batch);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
     delete ctx;
 }
 
@@ -829,10 +842,24 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     }
     // (a2) eps^-1 by blocked sweeps, Lambda = eps^-1 - I
     TRY(seg_begin(ctx, 2));
-    launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_imp, P.n_re, P.n_imp, at<double>(ctx, P.dinv_r),
+    if (P.n_re > 0) {
+        // the complex planes on the second stream: their small per-step kernels
+        // overlap the real planes' rank-64 updates and vice versa
+        HIPCK(hipEventRecord(ctx->fork, st));
+        HIPCK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        launch_sweep(ctx->side, at<double>(ctx, P.E), P.npad, 0, P.n_re, P.n_imp, at<double>(ctx, P.dinv_r),
+                     at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
+                     at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
+        LAUNCHCK();
+    }
+    launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_imp, 0, P.n_imp, at<double>(ctx, P.dinv_r),
                  at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
                  at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
     LAUNCHCK();
+    if (P.n_re > 0) {
+        HIPCK(hipEventRecord(ctx->join, ctx->side));
+        HIPCK(hipStreamWaitEvent(st, ctx->join, 0));
+    }
     TRY(seg_end(ctx));
     TRY(seg_begin(ctx, 3));
     launch_finalize_lambda(st, at<double>(ctx, P.E), P.npad, P.n_f, at<int>(ctx, P.idflag),
