@@ -42,7 +42,8 @@ struct Plan {
     Region eps, eps_g, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
         fit_m, w_im, w_re, coef, node, nterm, qpout, err;
     // transient regions (prepare only)
-    Region zr, zi, part, idflag, amax, sf, cw, cw64, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c, lh, ll,
+    Region zr, zi, part, idflag, amax, sf, cw, cw64, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c,
+        dscr_r, lh, ll,
         bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w, x32, yh, yl, t_pi, t_w,
         t_wf, pmap, imnode, imrest, tmat, rowsum;
     size_t total = 0;
@@ -455,12 +456,16 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
         add(P, P.t_wf, sizeof(int2) * P.n_twf);
     }
     add(P, P.E, sizeof(double) * (size_t)P.n_f * n2);
+    // real planes: sweeps with 128-wide pivots (64 x 128 panel blocks, and a
+    // 128 x 128 copy of each pivot block, swept with 64-wide pivots for its
+    // inverse); complex planes: 64-wide pivots
     add(P, P.dinv_r, sizeof(double) * (size_t)std::max(P.n_imp, 1) * blk);
-    add(P, P.pbuf_r, sizeof(double) * (size_t)P.n_imp * P.nblk * blk);
-    add(P, P.qbuf_r, sizeof(double) * (size_t)P.n_imp * P.nblk * blk);
+    add(P, P.pbuf_r, sizeof(double) * 2 * (size_t)P.n_imp * P.nblk * blk);
+    add(P, P.qbuf_r, sizeof(double) * 2 * (size_t)P.n_imp * P.nblk * blk);
     add(P, P.dinv_c, sizeof(double) * 2 * (size_t)std::max(P.n_re, 1) * blk);
     add(P, P.pbuf_c, sizeof(double) * 2 * (size_t)P.n_re * P.nblk * blk);
     add(P, P.qbuf_c, sizeof(double) * 2 * (size_t)P.n_re * P.nblk * blk);
+    add(P, P.dscr_r, sizeof(double) * 4 * (size_t)std::max(P.n_imp, 1) * blk);
     if (!f64) {
         add(P, P.lh, sizeof(uint16_t) * (size_t)P.n_f * n2);
         add(P, P.ll, sizeof(uint16_t) * (size_t)P.n_f * n2);
@@ -843,8 +848,10 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     // (a2) eps^-1 by blocked sweeps, Lambda = eps^-1 - I
     TRY(seg_begin(ctx, 2));
     if (P.n_re > 0) {
-        // the complex planes on the second stream: their small per-step kernels
-        // overlap the real planes' rank-64 updates and vice versa
+        // the complex planes on the second stream, with 64-wide pivots (eps is
+        // complex symmetric and indefinite there and no pivoting is done, so
+        // the smaller pivot blocks keep the element growth down); their small
+        // per-step kernels overlap the real planes' updates and vice versa
         HIPCK(hipEventRecord(ctx->fork, st));
         HIPCK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
         launch_sweep(ctx->side, at<double>(ctx, P.E), P.npad, 0, P.n_re, P.n_imp, at<double>(ctx, P.dinv_r),
@@ -852,9 +859,10 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
                      at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
         LAUNCHCK();
     }
-    launch_sweep(st, at<double>(ctx, P.E), P.npad, P.n_imp, 0, P.n_imp, at<double>(ctx, P.dinv_r),
-                 at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
-                 at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
+    // the real (positive definite) planes with 128-wide pivots
+    launch_sweep2(st, at<double>(ctx, P.E), P.npad, P.n_imp, 0, P.n_imp, at<double>(ctx, P.dscr_r), nullptr,
+                  at<double>(ctx, P.dinv_r), at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), nullptr, nullptr,
+                  nullptr, err);
     LAUNCHCK();
     if (P.n_re > 0) {
         HIPCK(hipEventRecord(ctx->join, ctx->side));

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(256) void k_sweep_panel(double* __restrict__ E, int
 // ---------------------------------------------------------------------------
 constexpr int U_KC = 16, U_LD = kNb + 2;
 
-template <bool C>
+// KW = panel width: 64 (one pivot block kb) or 128 (pivot blocks kb, kb + 1).
+template <bool C, int KW = kNb>
 __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, int npad, int cbase,
                                                       int kb, const double* __restrict__ pbuf,
                                                       const double* __restrict__ qbuf) {
@@ -188,9 +189,10 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     while (I * (I + 1) / 2 > t) --I;
     const int J = t - I * (I + 1) / 2;
-    if (I == kb || J == kb) return;
+    constexpr int NK = KW / kNb;                 // pivot blocks of this step
+    if ((I >= kb && I < kb + NK) || (J >= kb && J < kb + NK)) return;
     const int planes = C ? 2 : 1;
-    const int64_t blk = (int64_t)kNb * kNb, pstride = (int64_t)nblk * blk;
+    const int64_t blk = (int64_t)kNb * KW, pstride = (int64_t)nblk * blk;
     const double* Q = qbuf + ((int64_t)mat * planes * nblk + I) * blk;
     const double* P = pbuf + ((int64_t)mat * planes * nblk + J) * blk;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
@@ -213,13 +215,13 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
                 if (C) ei[bi][bj][r] = Ei[o];
             }
     v4d ar[2][2] = {}, ai[2][2] = {};
-    for (int k0 = 0; k0 < kNb; k0 += U_KC) {
+    for (int k0 = 0; k0 < KW; k0 += U_KC) {
 #pragma unroll
         for (int pl = 0; pl < planes; ++pl) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                sq[pl][kq + e][row] = Q[pl * pstride + row * kNb + k0 + kq + e];
-                sp[pl][kq + e][row] = P[pl * pstride + row * kNb + k0 + kq + e];
+                sq[pl][kq + e][row] = Q[pl * pstride + row * KW + k0 + kq + e];
+                sp[pl][kq + e][row] = P[pl * pstride + row * KW + k0 + kq + e];
             }
         }
         __syncthreads();
@@ -337,6 +339,167 @@ void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, in
                                kb, dinv_c, qbuf_c);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps of 128-wide pivot blocks K = {kb, kb + 1}: the same recursion with
+// D = A_KK (128 x 128), so each update is a rank-128 pass over the matrix and
+// the matrix streams through HBM half as often as with 64-wide pivots.
+// -D^-1 comes from sweeping a copy of A_KK with the 64-block kernels above.
+// Panel buffers hold 64 x 128 blocks: [mat][plane][nblk][64][128].
+// ---------------------------------------------------------------------------
+constexpr int kNb2 = 2 * kNb;
+
+// dscr[mat] (128 x 128, lower triangle) <- A_KK.
+template <bool C>
+__global__ __launch_bounds__(256) void k_sweep_gather(const double* __restrict__ E, int npad, int cbase, int kb,
+                                                      double* __restrict__ dscr) {
+    const int mat = blockIdx.x;
+    const int64_t n2 = (int64_t)npad * npad, d2 = (int64_t)kNb2 * kNb2;
+    double *Er, *Ei, *Dr, *Di;
+    mat_planes<C>(const_cast<double*>(E), n2, mat, cbase, Er, Ei);
+    mat_planes<C>(dscr, d2, mat, 0, Dr, Di);
+    const int k0 = kb * kNb;
+    for (int e = threadIdx.x; e < kNb2 * kNb2; e += 256) {
+        const int r = e / kNb2, c = e % kNb2;
+        if (c > r) continue;
+        const int64_t o = (int64_t)(k0 + r) * npad + k0 + c;
+        Dr[e] = Er[o];
+        if (C) Di[e] = Ei[o];
+    }
+}
+
+// P_i = A_iK (64 x 128, old values) and Q_i = P_i D^-1 for every block row
+// i outside K; D^-1 = -(swept copy), read from its lower triangle.
+template <bool C>
+__global__ __launch_bounds__(256) void k_sweep_panel2(const double* __restrict__ E, int npad, int cbase, int kb,
+                                                      const double* __restrict__ dscr, double* __restrict__ pbuf,
+                                                      double* __restrict__ qbuf) {
+    __shared__ double pr[kNb][kNb2 + 1];
+    __shared__ double pi[C ? kNb : 1][C ? kNb2 + 1 : 1];
+    const int ib = blockIdx.x, mat = blockIdx.y;
+    const int nblk = npad / kNb;
+    if (ib == kb || ib == kb + 1) return;
+    const int64_t n2 = (int64_t)npad * npad, d2 = (int64_t)kNb2 * kNb2;
+    double *Er, *Ei, *Dr, *Di;
+    mat_planes<C>(const_cast<double*>(E), n2, mat, cbase, Er, Ei);
+    mat_planes<C>(const_cast<double*>(dscr), d2, mat, 0, Dr, Di);
+    const int i0 = ib * kNb;
+    for (int e = threadIdx.x; e < kNb * kNb2; e += 256) {
+        const int a = e / kNb2, b = e % kNb2;          // row a of block i, column b of K
+        const int kc = kb * kNb + b;
+        const int64_t o = ib > kb ? (int64_t)(i0 + a) * npad + kc      // A_iK stored in the lower triangle
+                                  : (int64_t)kc * npad + i0 + a;       // or as A_Ki
+        pr[a][b] = Er[o];
+        if (C) pi[a][b] = Ei[o];
+    }
+    __syncthreads();
+    const int planes = C ? 2 : 1;
+    const int64_t blk = (int64_t)kNb * kNb2, pstride = (int64_t)nblk * blk;
+    double* Pb = pbuf + ((int64_t)mat * planes * nblk + ib) * blk;
+    double* Qb = qbuf + ((int64_t)mat * planes * nblk + ib) * blk;
+    // thread -> column c, rows r = t/128 + 2q
+    const int c = threadIdx.x & (kNb2 - 1), r0 = threadIdx.x >> 7;
+    double accr[32], acci[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) { accr[q] = 0.0; acci[q] = 0.0; }
+    for (int k = 0; k < kNb2; ++k) {
+        const int64_t o = k >= c ? (int64_t)k * kNb2 + c : (int64_t)c * kNb2 + k;
+        const double dre = -Dr[o];
+        const double dim = C ? -Di[o] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int r = r0 + 2 * q;
+            const double a = pr[r][k];
+            accr[q] += a * dre;
+            if (C) {
+                const double b = pi[r][k];
+                accr[q] -= b * dim;
+                acci[q] += a * dim + b * dre;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int r = r0 + 2 * q;
+        Qb[r * kNb2 + c] = accr[q];
+        Pb[r * kNb2 + c] = pr[r][c];
+        if (C) {
+            Qb[pstride + r * kNb2 + c] = acci[q];
+            Pb[pstride + r * kNb2 + c] = pi[r][c];
+        }
+    }
+}
+
+// A_iK <- Q_i for every block row i outside K; A_KK <- -D^-1 (the swept copy).
+template <bool C>
+__global__ __launch_bounds__(256) void k_sweep_writeback2(double* __restrict__ E, int npad, int cbase, int kb,
+                                                          const double* __restrict__ dscr,
+                                                          const double* __restrict__ qbuf) {
+    const int ib = blockIdx.x, mat = blockIdx.y;
+    const int nblk = npad / kNb;
+    const int planes = C ? 2 : 1;
+    const int64_t blk = (int64_t)kNb * kNb2, pstride = (int64_t)nblk * blk;
+    const int64_t n2 = (int64_t)npad * npad, d2 = (int64_t)kNb2 * kNb2;
+    double *Er, *Ei, *Dr, *Di;
+    mat_planes<C>(E, n2, mat, cbase, Er, Ei);
+    mat_planes<C>(const_cast<double*>(dscr), d2, mat, 0, Dr, Di);
+    const int k0 = kb * kNb, i0 = ib * kNb;
+    if (ib == kb + 1) return;
+    if (ib == kb) {
+        for (int e = threadIdx.x; e < kNb2 * kNb2; e += 256) {
+            const int r = e / kNb2, c = e % kNb2;
+            if (c > r) continue;
+            const int64_t o = (int64_t)(k0 + r) * npad + k0 + c;
+            Er[o] = Dr[e];
+            if (C) Ei[o] = Di[e];
+        }
+        return;
+    }
+    const double* Qb = qbuf + ((int64_t)mat * planes * nblk + ib) * blk;
+    for (int e = threadIdx.x; e < kNb * kNb2; e += 256) {
+        if (ib > kb) {
+            const int a = e / kNb2, b = e % kNb2;          // Q[a][b] -> A[i0 + a][k0 + b]
+            const int64_t o = (int64_t)(i0 + a) * npad + k0 + b;
+            Er[o] = Qb[a * kNb2 + b];
+            if (C) Ei[o] = Qb[pstride + a * kNb2 + b];
+        } else {
+            const int b = e / kNb, a = e % kNb;            // Q[a][b] -> A[k0 + b][i0 + a]
+            const int64_t o = (int64_t)(k0 + b) * npad + i0 + a;
+            Er[o] = Qb[a * kNb2 + b];
+            if (C) Ei[o] = Qb[pstride + a * kNb2 + b];
+        }
+    }
+}
+
+// Sweeps every block of n_mat real (C = false) or complex (C = true,
+// planes cbase + 2j) matrices in E with 128-wide pivots.  npad must be a
+// multiple of 128.  dscr: [n_mat][planes][128][128]; dinv, pbuf, qbuf as for
+// launch_sweep, with pbuf and qbuf twice as large.
+template <bool C>
+void launch_sweep2_t(hipStream_t s, double* E, int npad, int n_mat, int cbase, double* dscr, double* dinv,
+                     double* pbuf, double* qbuf, int* err) {
+    if (n_mat <= 0) return;
+    const int nblk = npad / kNb, T = nblk * (nblk + 1) / 2;
+    for (int kb = 0; kb < nblk; kb += 2) {
+        hipLaunchKernelGGL(k_sweep_gather<C>, dim3(n_mat), dim3(256), 0, s, E, npad, cbase, kb, dscr);
+        // -D^-1 of every pivot block: a 64-block sweep of the 128 x 128 copies
+        if (C) launch_sweep(s, dscr, kNb2, 0, n_mat, 0, nullptr, nullptr, nullptr, dinv, pbuf, qbuf, err);
+        else launch_sweep(s, dscr, kNb2, n_mat, 0, 0, dinv, pbuf, qbuf, nullptr, nullptr, nullptr, err);
+        hipLaunchKernelGGL(k_sweep_panel2<C>, dim3(nblk, n_mat), dim3(256), 0, s, E, npad, cbase, kb, dscr, pbuf,
+                           qbuf);
+        hipLaunchKernelGGL((k_sweep_update<C, kNb2>), dim3(T * n_mat), dim3(256), 0, s, E, npad, cbase, kb, pbuf,
+                           qbuf);
+        hipLaunchKernelGGL(k_sweep_writeback2<C>, dim3(nblk, n_mat), dim3(256), 0, s, E, npad, cbase, kb, dscr,
+                           qbuf);
+    }
+}
+
+void launch_sweep2(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dscr_r,
+                   double* dscr_c, double* dinv_r, double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c,
+                   double* qbuf_c, int* err) {
+    launch_sweep2_t<false>(s, E, npad, n_real, 0, dscr_r, dinv_r, pbuf_r, qbuf_r, err);
+    launch_sweep2_t<true>(s, E, npad, n_cplx, cbase, dscr_c, dinv_c, pbuf_c, qbuf_c, err);
 }
 
 }  // namespace cdwac

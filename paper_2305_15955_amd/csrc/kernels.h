@@ -97,6 +97,9 @@ void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* l
 // k_sweep.hip
 void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dinv_r,
                   double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c, double* qbuf_c, int* err);
+void launch_sweep2(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dscr_r,
+                   double* dscr_c, double* dinv_r, double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c,
+                   double* qbuf_c, int* err);
 
 // k_thiele.hip
 void launch_thiele_fit(hipStream_t s, int n_fit, int n_pts, const double* u, const double* w, double tol,

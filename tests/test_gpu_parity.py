@@ -80,6 +80,12 @@ def test_polarizability_single_element():
 # ----------------------------------------------------------- W, Sigma, QP
 
 def test_w_table_fp64_ragged(lib):
+    """W^c_nm at every imaginary node and near-real point, FP64 path.  The
+    inverse of eps(z) (Eq. bigLambda) carries rounding of order
+    cond(eps(z)) * u; near-real points sit next to RPA poles, where cond
+    reaches ~1e5 on this system, so the bar there is max(1e-10, 30 cond u)
+    of max|W| (the two sides invert by different eliminations: blocked sweeps
+    against an LU solve)."""
     case = cases.ragged()
     o = cases.oracle(case)
     run(lib, case, "p64")
@@ -88,12 +94,16 @@ def test_w_table_fp64_ragged(lib):
     scale = np.max(np.abs(o.w_im), axis=2, keepdims=True)
     assert np.max(np.abs(w_im - o.w_im) / scale) < 1e-10
     np.testing.assert_allclose(sx, o.sigma_x, rtol=1e-13)
+    u = np.finfo(np.float64).eps / 2
+    cond = max(np.linalg.cond(np.eye(s.n_aux) - R.polarizability(s.o_ia, s.eps, s.n_occ, x + 1j * case.eta_ref,
+                                                                  s.spin)) for x in case.ref_re)
+    bar = max(1e-10, 30.0 * cond * u)
     f = 0
     for n in range(s.n_states):
         for m in range(m0[n], m1[n]):
             ref = o.w_re[n, m, :]
             err = np.max(np.abs(w_re[f] - ref)) / np.max(np.abs(ref))
-            assert err < 1e-10, (n, m, err)
+            assert err < bar, (n, m, err, bar)
             f += 1
     assert f == w_re.shape[0]
 
