@@ -295,11 +295,15 @@ int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double omega_lo
 
 /* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------
  * Parameter vector (CDWAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64],
- * b2[64], W3[1][64], b3[1].  Features of a state (Ha): eps_n, eps_F,
- * Sigma^x - v^xc, Re Sigma^c at eps_n + {-3, -1, 1, 3}/16, and the
- * fixed-point guess Sigma^x - v^xc + (two central samples)/2; the network predicts
- * eps^QP - eps_n.  Inputs are standardised with (mu, sd) and the output is
- * y * out_sd + out_mu. */
+ * b2[64], W3[1][64], b3[1].  The root search evaluates f(w) = w - eps_n -
+ * Sigma_n(w) + v^xc_n at w0 = eps_n and w1 = w0 - f(w0), which give the secant
+ * step w2.  Features of a state (Ha): eps_n, eps_F, Sigma^x - v^xc,
+ * Re Sigma^c(w0), Re Sigma^c(w1), w1 - w0, f(w1), w2 - w1; the network predicts
+ * the remaining correction w* - w2, so the seed needs no self-energy
+ * evaluation beyond those two.  Inputs are standardised with (mu, sd) and the
+ * output is y * out_sd + out_mu.  A seed with |f| <= mlp_accept is the root
+ * (flag CDWAC_FLAG_MLP_ACCEPTED); otherwise the secant continues from w1 and
+ * the seed, and if that search fails the plain one from w0 and w1 runs. */
 #define CDWAC_MLP_NIN 8
 #define CDWAC_MLP_NPARAM 4801
 

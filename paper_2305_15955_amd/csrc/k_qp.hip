@@ -147,69 +147,64 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
 
     double root = 0.0, zf = 0.0;
     bool done = false;
-    double w0 = e_n, f0 = 0.0, w1 = 0.0;
-    bool seeded = false;
-    if (A.use_mlp) {
-        // features: eps_n, eps_F, Sigma^x - v^xc, Re Sigma^c at eps_n + {-3, -1, 1, 3}/16 Ha,
-        // fixed-point guess Sigma^x - v^xc + mean of the two central samples
-        float feat[8];
-        double sc[4];
-        for (int j = 0; j < 4; ++j) {
-            ++n_eval;
-            sc[j] = sigma_total(A, s, e_n + (2 * j - 3) / 16.0, sh) - A.sigx[s];
+    // secant from omega_0 = eps_n and one fixed-point step
+    double w0 = e_n, f0 = f(w0), w1 = w0 - f0, f1 = 0.0;
+    bool in1 = lo <= w1 && w1 <= hi, have_f1 = false;
+    if (in1) {
+        f1 = f(w1);
+        have_f1 = true;
+    }
+    // secant iteration from the pair (xa, fa), (xb, fb); on convergence with a
+    // physical Z factor the root and Z are taken
+    auto secant = [&](double xa, double fa, double xb, double fb) {
+        bool ok = false;
+        for (int it = 0; it < A.qp_maxit; ++it) {
+            if (fb == fa) break;
+            const double xc = xb - fb * (xb - xa) / (fb - fa);
+            if (!(lo <= xc && xc <= hi)) break;
+            xa = xb;
+            fa = fb;
+            xb = xc;
+            fb = f(xb);
+            if (fabs(xb - xa) < A.qp_tol && fabs(fb) < kFTol) {
+                ok = true;
+                break;
+            }
         }
-        double d0 = A.sigx[s] - vxc;
-        double raw[8] = {e_n, A.eps_f, d0, sc[0], sc[1], sc[2], sc[3], d0 + 0.5 * (sc[1] + sc[2])};
+        if (!ok) return false;
+        const double z = z_factor(xb);
+        if (!(0.0 < z && z <= 1.0)) return false;
+        root = xb;
+        zf = z;
+        return true;
+    };
+    if (A.use_mlp && in1) {
+        // learned seed: from the two evaluations above (Sigma^c at eps_n and at
+        // omega_1) and the secant step they give, the network predicts the
+        // remaining correction omega* - omega_2
+        const double sx = A.sigx[s];
+        const double sc0 = w0 - e_n + vxc - f0 - sx, sc1 = w1 - e_n + vxc - f1 - sx;
+        const double w2 = f1 != f0 ? w1 - f1 * (w1 - w0) / (f1 - f0) : w1;
+        const double raw[8] = {e_n, A.eps_f, sx - vxc, sc0, sc1, w1 - w0, f1, w2 - w1};
+        float feat[8];
         for (int i = 0; i < 8; ++i) feat[i] = (float)((raw[i] - A.mlp_mu[i]) / A.mlp_sd[i]);
-        float y = mlp_one(A.mlp_theta, feat, sh);
-        double seed = e_n + (double)y * A.mlp_out_sd + A.mlp_out_mu;
+        const float y = mlp_one(A.mlp_theta, feat, sh);
+        const double seed = w2 + (double)y * A.mlp_out_sd + A.mlp_out_mu;
         if (seed >= lo && seed <= hi) {
-            double fs = f(seed);
+            const double fs = f(seed);
             if (fabs(fs) <= A.mlp_accept) {
                 root = seed;
                 zf = z_factor(seed);
                 flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
                 done = true;
             } else {
-                w0 = seed;
-                f0 = fs;
-                w1 = w0 - f0;
-                seeded = true;
+                // the secant continues from omega_1 and the seed
+                done = secant(w1, f1, seed, fs);
             }
         }
     }
-    if (!done && !seeded) {
-        w0 = e_n;
-        f0 = f(w0);
-        w1 = w0 - f0;
-    }
-    if (!done) {
-        bool ok = false;
-        if (lo <= w1 && w1 <= hi) {
-            double f1 = f(w1);
-            for (int it = 0; it < A.qp_maxit; ++it) {
-                if (f1 == f0) break;
-                double w2 = w1 - f1 * (w1 - w0) / (f1 - f0);
-                if (!(lo <= w2 && w2 <= hi)) break;
-                w0 = w1;
-                f0 = f1;
-                w1 = w2;
-                f1 = f(w1);
-                if (fabs(w1 - w0) < A.qp_tol && fabs(f1) < kFTol) {
-                    ok = true;
-                    break;
-                }
-            }
-        }
-        if (ok) {
-            double z = z_factor(w1);
-            if (0.0 < z && z <= 1.0) {
-                root = w1;
-                zf = z;
-                done = true;
-            }
-        }
-    }
+    // the plain search from omega_0 and omega_1 (also where a seeded search failed)
+    if (!done && have_f1) done = secant(w0, f0, w1, f1);
     if (!done) {
         flags |= CDWAC_FLAG_FALLBACK_DEV;
         const int n = (int)ceil((hi - lo) / kScanStep);

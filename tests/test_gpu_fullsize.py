@@ -149,3 +149,61 @@ def test_naux5000_sampled_pi_and_properties(lib):
         else:
             # rejected seed: the secant from it reaches the plain path's root
             assert d[n] <= 1e-8 * abs(qp["f16x3"][n]) / MEV, (n, o)
+
+
+def test_deploy_naux6600_learned_seed(lib):
+    """The learned seed at its deployment size (N_mo = 2000, N_aux = 6600, 24
+    core states; O^{ia} is 29 GB): the benchmark mode (Pi in one fp16
+    product, W in the fp16 split, skeleton nodes) with and without the seed,
+    against the fp16 split (FP32-level Pi) without it.  Every root has Z in
+    (0.5, 1] and |f| <= 1e-8 Ha, or <= 1 meV where the seed is accepted (the
+    secant is the fallback and the judge); all states within 1 meV of the
+    reference; an accepted seed ends the search after 5 self-energy
+    evaluations and a rejected one costs at most one more than the plain
+    search.  Sampled Pi entries against the oracle's one-by-one definition."""
+    import torch
+    case = cases.workload("mlp_deploy_naux6600")
+    s = case.system
+    print("deploy workload drawn", flush=True)
+    dev = torch.device("cuda", 0)
+    o_ia = torch.from_numpy(s.o_ia).to(dev)
+    o_nm = torch.from_numpy(s.o_nm).to(dev)
+    sysc, keep = lib.make_system(s, o_ia_dev=o_ia, o_nm_dev=o_nm)
+    rng = np.random.default_rng(6)
+    pairs = [(int(p), int(q)) for p, q in zip(rng.integers(0, s.n_aux, 8), rng.integers(0, s.n_aux, 8))]
+    pairs += [(0, 0), (s.n_aux - 1, s.n_aux - 1)]
+    zs = [1j * case.freq[9]]
+    for prec, tol in (("p64", 1e-12), ("f16", 3e-5)):
+        pis = lib.cdwac_polarizability(sysc, zs, prec=prec)
+        ref = R.polarizability_entries(s.o_ia, s.eps, s.n_occ, zs[0], s.spin, pairs)
+        got = np.array([pis[0][p, q] for p, q in pairs])
+        scale = np.max(np.abs(np.diagonal(pis[0])))
+        print(prec, "max |dPi| / max|diag|", np.max(np.abs(got - ref)) / scale, flush=True)
+        assert np.max(np.abs(got - ref)) <= tol * scale, prec
+        del pis
+    mdl = np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                               "paper_2305_15955_amd", "seed_model.npz"))
+    lib.cdwac_mlp_set_model(mdl["theta"], mdl["mu"], mdl["sd"], float(mdl["out_mu"]), float(mdl["out_sd"]))
+    res = {}
+    for key, prec, mlp in (("ref", "f16x3", False), ("plain", "f16", False), ("seeded", "f16", True)):
+        prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                    pade_tol=1e-9, prec=prec, use_mlp_seed=mlp, mlp_accept=MEV,
+                                    freq_rank_tol=1e-10)
+        lib.cdwac_prepare(sysc, prm)
+        res[key] = lib.cdwac_qp(s.n_states)
+        print(key, "evaluations", [o["n_evals"] for o in res[key]], flush=True)
+    qref = np.array([o["qp"] for o in res["ref"]])
+    for key in ("plain", "seeded"):
+        for n, o in enumerate(res[key]):
+            accepted = bool(o["flags"] & R.FLAG_MLP_ACCEPTED)
+            assert not o["flags"] & R.FLAG_NOROOT and 0.5 < o["z"] <= 1.0, (key, n, o)
+            assert abs(o["residual"]) <= (MEV if accepted else 1e-8), (key, n, o)
+            assert abs(o["qp"] - qref[n]) <= MEV, (key, n, o["qp"], qref[n])
+    n_acc = sum(bool(o["flags"] & R.FLAG_MLP_ACCEPTED) for o in res["seeded"])
+    mean_plain = np.mean([o["n_evals"] for o in res["plain"]])
+    mean_seeded = np.mean([o["n_evals"] for o in res["seeded"]])
+    print(f"seed accepted for {n_acc} of {s.n_states}; mean evaluations {mean_plain:.2f} -> {mean_seeded:.2f}")
+    for o0, o1 in zip(res["plain"], res["seeded"]):
+        assert o1["n_evals"] <= o0["n_evals"] + 1
+        if o1["flags"] & R.FLAG_MLP_ACCEPTED:
+            assert o1["n_evals"] == 5
