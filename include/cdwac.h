@@ -307,8 +307,10 @@ int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double omega_lo
 #define CDWAC_MLP_NIN 8
 #define CDWAC_MLP_NPARAM 4801
 
-/* Installs the seed model used by cdwac_qp when use_mlp_seed = 1.
- * theta: host [4801]; mu, sd: host [8]; out_mu, out_sd: scalars. */
+/* Installs the seed model used by cdwac_qp when use_mlp_seed = 1 (copied;
+ * the caller keeps its arrays).  theta: host [4801]; mu, sd: host [8];
+ * out_mu, out_sd: scalars.  CDWAC_EINVAL for NULL arrays, sd <= 0, out_sd <= 0
+ * or non-finite mu, out_mu, out_sd. */
 int cdwac_mlp_set_model(cdwac_ctx *ctx, const float *theta, const float *mu, const float *sd,
                         float out_mu, float out_sd);
 

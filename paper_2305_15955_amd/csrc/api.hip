@@ -1562,7 +1562,8 @@ int cdwac_mlp_set_model(cdwac_ctx* ctx, const float* theta, const float* mu, con
     if (!theta || !mu || !sd) return fail(ctx, CDWAC_EINVAL, "NULL model array");
     for (int i = 0; i < 8; ++i)
         if (!(sd[i] > 0.f) || !std::isfinite(mu[i])) return fail(ctx, CDWAC_EINVAL, "feature scale must be > 0");
-    if (!(out_sd > 0.f)) return fail(ctx, CDWAC_EINVAL, "out_sd must be > 0");
+    if (!(out_sd > 0.f) || !std::isfinite(out_sd) || !std::isfinite(out_mu))
+        return fail(ctx, CDWAC_EINVAL, "out_sd must be finite and > 0, out_mu finite");
     HIPCK(hipSetDevice(ctx->device));
     HIPCK(hipMemcpy(ctx->mlp_theta, theta, sizeof(float) * kMlpParams, hipMemcpyHostToDevice));
     memcpy(ctx->mlp_mu, mu, sizeof ctx->mlp_mu);
