@@ -454,6 +454,29 @@ def test_error_paths(lib):
     fresh.close()
 
 
+def test_empty_inputs(lib):
+    """A system without core states and an empty batch are rejected with
+    CDWAC_EINVAL (the header requires n_states >= 1 and n_sys >= 1); an MLP
+    forward pass over zero samples is a no-op.  The context stays usable."""
+    import dataclasses
+    cdwac = cdwac_mod()
+    case = cases.ragged()
+    s = case.system
+    empty = dataclasses.replace(s, state_idx=np.zeros(0, np.int32), o_nm=s.o_nm[:0])
+    e_case = dataclasses.replace(case, system=empty, lo=case.lo[:0], hi=case.hi[:0])
+    with pytest.raises(cdwac.CdwacError) as e:
+        run(lib, e_case, "p64")
+    assert e.value.code == cdwac.CDWAC_EINVAL
+    with pytest.raises(cdwac.CdwacError) as e:
+        lib.cdwac_solve_batch([], [])
+    assert e.value.code == cdwac.CDWAC_EINVAL
+    y = lib.cdwac_mlp_forward(np.zeros(4801, np.float32), np.zeros((0, 8), np.float32))
+    assert y.shape == (0,)
+    run(lib, case, "p64")
+    out = lib.cdwac_qp(s.n_states)
+    assert all(o["flags"] == 0 for o in out)
+
+
 def test_skeleton_nodes_fall_back_when_excitations_exceed_the_range(lib):
     """With very strong screening the RPA excitations exceed the range the
     skeleton decomposition assumes; the range check after Pi then re-runs
