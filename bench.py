@@ -186,8 +186,9 @@ def main():
     ap.add_argument("--workload", default="precision_naux5000")
     ap.add_argument("--prec", default="f16", choices=["f16", "f16x3", "b16x3", "b16", "p64"])
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 GPU path")
-    ap.add_argument("--rank-tol", type=float, default=1e-10,
-                    help="imaginary-node decomposition tolerance of the 16-bit path (0: every node)")
+    ap.add_argument("--rank-tol", type=float, default=None,
+                    help="imaginary-node decomposition tolerance of the 16-bit path (0: every node; "
+                         "default: the mode's entry of cdwac.SKELETON_TOL)")
     ap.add_argument("--near-real-f64", action="store_true",
                     help="16-bit modes: Pi at the near-real reference points on the FP64 path")
     ap.add_argument("--no-mlp", action="store_true")
@@ -201,13 +202,15 @@ def main():
         print(json.dumps(scaling([60, 120, 240, 480, 960], 240)), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no "
-              "multi-GPU mode in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
+              "multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2305_15955_amd import cdwac, synth
 
+    if args.rank_tol is None:
+        args.rank_tol = cdwac.SKELETON_TOL[args.prec]
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
     spec, s, freq, wts, ref_im, ref_re, lo, hi = build_inputs(args.workload)

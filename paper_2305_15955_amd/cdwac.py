@@ -28,6 +28,12 @@ CDWAC_P64, CDWAC_B16X3, CDWAC_B16, CDWAC_F16X3, CDWAC_F16 = 0, 1, 2, 3, 4
 FLAG_NOROOT, FLAG_FALLBACK, FLAG_MLP_ACCEPTED = 1, 2, 4
 MLP_NPARAM = 4801
 PREC = {"p64": CDWAC_P64, "b16x3": CDWAC_B16X3, "b16": CDWAC_B16, "f16x3": CDWAC_F16X3, "f16": CDWAC_F16}
+# Skeleton-node tolerance (freq_rank_tol) of each 16-bit mode, set at the W
+# error the mode's own contractions leave on the imaginary axis, so that the
+# frequency interpolation adds nothing visible: one fp16 product 1.6e-6 of
+# max|W|, the fp16 split 2e-8 (measured against the FP64 path at N_aux = 5000).
+# The bf16 modes, not measured, take the fp16 values.
+SKELETON_TOL = {"f16": 1e-6, "b16": 1e-6, "f16x3": 1e-8, "b16x3": 1e-8, "p64": 0.0}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

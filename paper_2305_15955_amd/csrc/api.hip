@@ -812,8 +812,12 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     } else {
         const int* pm = at<int>(ctx, P.pmap);
         const int n_pi16 = P.nr64 ? P.n_imp : P.n_f;   // planes on the 16-bit path
-        for (int f0 = 0; f0 < n_pi16; f0 += P.nb) {
-            const int nfb = std::min(P.nb, n_pi16 - f0);
+        // as few batches as the Y buffers allow, of near-equal size, so that no
+        // launch is a small remainder that leaves the chip partly idle
+        const int n_batch = (n_pi16 + P.nb - 1) / P.nb;
+        const int per_batch = n_batch > 0 ? (n_pi16 + n_batch - 1) / n_batch : 1;
+        for (int f0 = 0; f0 < n_pi16; f0 += per_batch) {
+            const int nfb = std::min(per_batch, n_pi16 - f0);
             TRY(seg_begin(ctx, 7));
             launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, pm + f0, nfb,
                             at<uint16_t>(ctx, P.yh), pi_split ? at<uint16_t>(ctx, P.yl) : nullptr);
@@ -854,9 +858,11 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
         // per-step kernels overlap the real planes' updates and vice versa
         HIPCK(hipEventRecord(ctx->fork, st));
         HIPCK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        // (16-bit modes: complex products in three real ones, whose rounding
+        // stays far below the error the 16-bit contraction leaves in eps)
         launch_sweep(ctx->side, at<double>(ctx, P.E), P.npad, 0, P.n_re, P.n_imp, at<double>(ctx, P.dinv_r),
                      at<double>(ctx, P.pbuf_r), at<double>(ctx, P.qbuf_r), at<double>(ctx, P.dinv_c),
-                     at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err);
+                     at<double>(ctx, P.pbuf_c), at<double>(ctx, P.qbuf_c), err, !f64);
         LAUNCHCK();
     }
     // the real (positive definite) planes with 128-wide pivots

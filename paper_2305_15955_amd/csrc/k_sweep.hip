@@ -171,11 +171,16 @@ __global__ __launch_bounds__(256) void k_sweep_panel(double* __restrict__ E, int
 // 3. Rank-64 update of every lower tile (I, J), I, J != k:
 //    A_IJ -= Q_I P_J^T  (complex: re -= Qr Pr^T - Qi Pi^T, im -= Qr Pi^T + Qi Pr^T)
 //    FP64 MFMA 16x16x4, 64 x 64 tile, 4 waves of 32 x 32.
+//    With M3 the complex product takes three real products instead of four
+//    (Gauss): T1 = Qr Pr^T, T2 = Qi Pi^T, T3 = (Qr + Qi)(Pr + Pi)^T, re = T1 - T2,
+//    im = T3 - T1 - T2.  Its rounding error is bounded by (|Qr| + |Qi|)(|Pr| + |Pi|)
+//    u per term, the size of the real part's, so it is used where the inputs
+//    carry 16-bit contraction errors far above that.
 // ---------------------------------------------------------------------------
 constexpr int U_KC = 16, U_LD = kNb + 2;
 
 // KW = panel width: 64 (one pivot block kb) or 128 (pivot blocks kb, kb + 1).
-template <bool C, int KW = kNb>
+template <bool C, int KW = kNb, bool M3 = false>
 __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, int npad, int cbase,
                                                       int kb, const double* __restrict__ pbuf,
                                                       const double* __restrict__ qbuf) {
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
                 er[bi][bj][r] = Er[o];
                 if (C) ei[bi][bj][r] = Ei[o];
             }
-    v4d ar[2][2] = {}, ai[2][2] = {};
+    v4d ar[2][2] = {}, ai[2][2] = {}, a2[M3 ? 2 : 1][M3 ? 2 : 1] = {};
     for (int k0 = 0; k0 < KW; k0 += U_KC) {
 #pragma unroll
         for (int pl = 0; pl < planes; ++pl) {
@@ -246,14 +251,26 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
                     qb[b] = sq[C ? 1 : 0][k][wr * 32 + b * 16 + lr];
                     pb[b] = sp[C ? 1 : 0][k][wc * 32 + b * 16 + lr];
                 }
+                if (M3) {
 #pragma unroll
-                for (int bi = 0; bi < 2; ++bi)
+                    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < 2; ++bj) {
-                        ar[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-qb[bi], pb[bj], ar[bi][bj], 0, 0, 0);
-                        ai[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[bi], pb[bj], ai[bi][bj], 0, 0, 0);
-                        ai[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(qb[bi], pa[bj], ai[bi][bj], 0, 0, 0);
-                    }
+                        for (int bj = 0; bj < 2; ++bj) {
+                            a2[M3 ? bi : 0][M3 ? bj : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                qb[bi], pb[bj], a2[M3 ? bi : 0][M3 ? bj : 0], 0, 0, 0);
+                            ai[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[bi] + qb[bi], pa[bj] + pb[bj],
+                                                                             ai[bi][bj], 0, 0, 0);
+                        }
+                } else {
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj) {
+                            ar[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-qb[bi], pb[bj], ar[bi][bj], 0, 0, 0);
+                            ai[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[bi], pb[bj], ai[bi][bj], 0, 0, 0);
+                            ai[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(qb[bi], pa[bj], ai[bi][bj], 0, 0, 0);
+                        }
+                }
             }
         }
         __syncthreads();
@@ -267,8 +284,14 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
                 int P_ = I * kNb + wr * 32 + bi * 16 + lk + 4 * r;
                 int Q_ = J * kNb + wc * 32 + bj * 16 + lr;
                 int64_t o = (int64_t)P_ * npad + Q_;
-                Er[o] = er[bi][bj][r] - ar[bi][bj][r];
-                if (C) Ei[o] = ei[bi][bj][r] - ai[bi][bj][r];
+                if (C && M3) {
+                    const double t1 = ar[bi][bj][r], t2 = a2[M3 ? bi : 0][M3 ? bj : 0][r];
+                    Er[o] = er[bi][bj][r] - (t1 - t2);
+                    Ei[o] = ei[bi][bj][r] - (ai[bi][bj][r] - t1 - t2);
+                } else {
+                    Er[o] = er[bi][bj][r] - ar[bi][bj][r];
+                    if (C) Ei[o] = ei[bi][bj][r] - ai[bi][bj][r];
+                }
             }
 }
 
@@ -316,7 +339,7 @@ __global__ __launch_bounds__(256) void k_sweep_writeback(double* __restrict__ E,
 // Sweeps every block of n_real real and n_cplx complex matrices in E.
 void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dinv_r,
                   double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c, double* qbuf_c,
-                  int* err) {
+                  int* err, bool gauss3) {
     const int nblk = npad / kNb, T = nblk * (nblk + 1) / 2;
     for (int kb = 0; kb < nblk; ++kb) {
         if (n_real > 0) {
@@ -333,8 +356,12 @@ void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, in
                                err);
             hipLaunchKernelGGL(k_sweep_panel<true>, dim3(nblk, n_cplx), dim3(256), 0, s, E, npad, cbase, kb,
                                dinv_c, pbuf_c, qbuf_c);
-            hipLaunchKernelGGL(k_sweep_update<true>, dim3(T * n_cplx), dim3(256), 0, s, E, npad, cbase, kb,
-                               pbuf_c, qbuf_c);
+            if (gauss3)
+                hipLaunchKernelGGL((k_sweep_update<true, kNb, true>), dim3(T * n_cplx), dim3(256), 0, s, E, npad,
+                                   cbase, kb, pbuf_c, qbuf_c);
+            else
+                hipLaunchKernelGGL(k_sweep_update<true>, dim3(T * n_cplx), dim3(256), 0, s, E, npad, cbase, kb,
+                                   pbuf_c, qbuf_c);
             hipLaunchKernelGGL(k_sweep_writeback<true>, dim3(nblk, n_cplx), dim3(256), 0, s, E, npad, cbase,
                                kb, dinv_c, qbuf_c);
         }

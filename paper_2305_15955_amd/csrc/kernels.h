@@ -96,7 +96,8 @@ void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* l
 
 // k_sweep.hip
 void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dinv_r,
-                  double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c, double* qbuf_c, int* err);
+                  double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c, double* qbuf_c, int* err,
+                  bool gauss3 = false);
 void launch_sweep2(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dscr_r,
                    double* dscr_c, double* dinv_r, double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c,
                    double* qbuf_c, int* err);

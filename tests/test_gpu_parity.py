@@ -133,7 +133,8 @@ def test_sigma_and_qp_fp64(lib, which):
 
 
 @pytest.mark.parametrize("prec,tol_mev,rank_tol", [("f16x3", 1.0, 0.0), ("f16x3", 1.0, 1e-10),
-                                                    ("f16", 1.0, 1e-10)])
+                                                    ("f16", 1.0, 1e-10), ("f16x3", 1.0, 1e-8),
+                                                    ("f16", 1.0, 1e-6)])
 def test_qp_reduced_precision_within_1mev(lib, prec, tol_mev, rank_tol):
     for case in (cases.ragged(n_pade=32), cases.workload("fp64_1core_nmo60")):
         o = cases.oracle(case)
