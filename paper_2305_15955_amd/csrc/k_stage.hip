@@ -141,9 +141,11 @@ __global__ void k_prescale(const float* __restrict__ x32, int npad, int64_t kpad
                     h[e] = h0 | ((uint32_t)h1 << 16);
                     l[e] = l0 | ((uint32_t)l1 << 16);
                 }
+                // streaming stores: the planes are far larger than the caches and
+                // are next read by the contraction, not by this kernel
                 const int64_t word = (rb * kw + sp * 4 + g) * 64 + lane;
-                oh[word] = make_uint4(h[0], h[1], h[2], h[3]);
-                if (yl) ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
+                __builtin_nontemporal_store(v4u{h[0], h[1], h[2], h[3]}, reinterpret_cast<v4u*>(oh + word));
+                if (yl) __builtin_nontemporal_store(v4u{l[0], l[1], l[2], l[3]}, reinterpret_cast<v4u*>(ol + word));
             }
         }
     }
