@@ -75,6 +75,7 @@ struct HostState {
 
 struct cdwac_ctx {
     int device = 0;
+    int n_cu = 256;   // compute units of the device
     hipStream_t stream = nullptr;
     std::string err;
     void* ws_user = nullptr;
@@ -626,7 +627,9 @@ int cdwac_ctx_create(cdwac_ctx** out, int device, void* hip_stream) {
     if (hipSetDevice(device) != hipSuccess || hipMalloc(&ctx->mlp_theta, sizeof(float) * kMlpParams) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess ||
+        hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        ctx->n_cu < 1) {
         if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
         if (ctx->side) (void)hipStreamDestroy(ctx->side);
         if (ctx->fork) (void)hipEventDestroy(ctx->fork);
@@ -812,10 +815,28 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     } else {
         const int* pm = at<int>(ctx, P.pmap);
         const int n_pi16 = P.nr64 ? P.n_imp : P.n_f;   // planes on the 16-bit path
-        // as few batches as the Y buffers allow, of near-equal size, so that no
-        // launch is a small remainder that leaves the chip partly idle
-        const int n_batch = (n_pi16 + P.nb - 1) / P.nb;
-        const int per_batch = n_batch > 0 ? (n_pi16 + n_batch - 1) / n_batch : 1;
+        // Batches of near-equal size within the Y buffers.  Every tile keeps one
+        // CU busy for the same time, so a launch takes ceil(tiles / CUs) waves
+        // of workgroups; take the split with the fewest waves in total (a last
+        // wave that is mostly empty costs as much as a full one), then the
+        // fewest launches.
+        const int min_batches = (n_pi16 + P.nb - 1) / P.nb;
+        auto waves = [&](int per) {
+            int64_t w = 0;
+            for (int f0 = 0; f0 < n_pi16; f0 += per)
+                w += ((int64_t)std::min(per, n_pi16 - f0) * P.n_tpi + ctx->n_cu - 1) / ctx->n_cu;
+            return w;
+        };
+        int per_batch = std::max(1, (n_pi16 + std::max(min_batches, 1) - 1) / std::max(min_batches, 1));
+        int64_t best = waves(per_batch);
+        for (int nbat = min_batches + 1; nbat <= std::min(n_pi16, min_batches + 4); ++nbat) {
+            const int per = (n_pi16 + nbat - 1) / nbat;
+            const int64_t w = waves(per);
+            if (w < best) {
+                best = w;
+                per_batch = per;
+            }
+        }
         for (int f0 = 0; f0 < n_pi16; f0 += per_batch) {
             const int nfb = std::min(per_batch, n_pi16 - f0);
             TRY(seg_begin(ctx, 7));
