@@ -62,6 +62,80 @@ def measured_traffic(prec, workload, launches, planes):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def full_cd_qp(lib, sysc, prm, system, state, sigma_x):
+    """Full-CD QP energy of one state: the secant of the library's root search
+    (omega_0 = eps_n, one fixed-point step, |d omega| < 1e-10 Ha) over
+    cdwac_sigma_cd, which evaluates W directly at every residue; v^xc = Sigma^x."""
+    e_n = float(system.eps[system.state_idx[state]])
+    f = lambda w: w - e_n - lib.cdwac_sigma_cd(sysc, prm, state, w)[0] + sigma_x
+    w0, f0 = e_n, f(e_n)
+    w1 = w0 - f0
+    f1 = f(w1)
+    for _ in range(50):
+        if f1 == f0:
+            break
+        w2 = w1 - f1 * (w1 - w0) / (f1 - f0)
+        w0, f0, w1 = w1, f1, w2
+        f1 = f(w1)
+        if abs(w1 - w0) < 1e-10:
+            break
+    return w1
+
+
+def heatmap(n_systems, cores, vals, n_im, n_freq, mo_range=(90, 150)):
+    """CD-WAC against full CD as the refined reference set grows (Sec. 3.3,
+    the study behind the recommended CD-WAC(20, 20, 200)): mean absolute error
+    in meV of the core QP energies over seeded synthetic systems, for every
+    CD-WAC(N_core, N_valence, N_Im) on an n_freq-node imaginary grid, FP64 path
+    on both sides."""
+    from paper_2305_15955_amd import cdwac, grids, synth
+    lib = cdwac.Cdwac(0)
+    freq, wts = grids.gauss_legendre_imag(n_freq)
+    err = np.full((len(cores), len(vals)), 0.0)
+    worst = np.full((len(cores), len(vals)), 0.0)
+    lost = np.zeros((len(cores), len(vals)), np.int64)
+    n_states = 0
+    sizes = []
+    for j in range(n_systems):
+        rng = np.random.default_rng(700 + j)
+        n_mo = int(rng.integers(mo_range[0], mo_range[1] + 1))
+        n_occ = max(3, round(n_mo / 6))
+        n_core = int(rng.integers(1, 4))
+        n_aux = round(3.3 * n_mo)
+        k = n_occ * (n_mo - n_occ)
+        s = synth.make_system(n_mo, n_occ, n_aux, n_core, math.sqrt(synth.SCREENING / k), kappa=0.2, seed=700 + j)
+        sizes.append([n_mo, n_aux, n_core])
+        lo, hi = grids.windows(s.eps, s.state_idx, 30.0)
+        sysc, keep = lib.make_system(s)
+        ref_im, ref_re = grids.cdwac_setting(s.eps, s.n_occ, s.state_idx, lo, hi, 20, 20, n_im, n_freq)
+        prm, arrs = lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec="p64")
+        out = lib.cdwac_solve(sysc, prm)
+        cd = [full_cd_qp(lib, sysc, prm, s, n, float(out[n]["sigma_x"])) for n in range(s.n_states)]
+        for a, nc in enumerate(cores):
+            for b, nv in enumerate(vals):
+                ref_im, ref_re = grids.cdwac_setting(s.eps, s.n_occ, s.state_idx, lo, hi, nc, nv, n_im, n_freq)
+                prm, arrs = lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec="p64")
+                out = lib.cdwac_solve(sysc, prm)
+                for n in range(s.n_states):
+                    d = abs(out[n]["qp"] - cd[n]) * synth.HARTREE_EV * 1e3
+                    if not np.isfinite(d):
+                        lost[a, b] += 1
+                        continue
+                    err[a, b] += d
+                    worst[a, b] = max(worst[a, b], d)
+        n_states += s.n_states
+        log(f"heatmap system {j + 1}/{n_systems}: N_mo={n_mo}, {s.n_states} core states")
+        del keep
+    lib.close()
+    counted = n_states - lost
+    return {"metric": "MAE of CD-WAC(N_core, N_valence, N_Im) against full CD, core QP energies",
+            "unit": "meV", "n_im": n_im, "n_freq": n_freq, "n_core": list(cores), "n_valence": list(vals),
+            "systems": sizes, "states": n_states,
+            "mae_mev": (err / np.maximum(counted, 1)).tolist(), "max_mev": worst.tolist(),
+            "states_without_root": lost.tolist(),
+            "data": "synthetic (seeded Gaussian RI coefficients, no molecule)"}
+
+
 def build_inputs(name):
     from paper_2305_15955_amd import grids, synth
     spec = synth.WORKLOADS[name]
@@ -197,9 +271,15 @@ def main():
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     ap.add_argument("--scaling", action="store_true",
                     help="instead of the benchmark: full CD against CD-WAC as N_mo grows (one JSON line)")
+    ap.add_argument("--heatmap", action="store_true",
+                    help="instead of the benchmark: CD-WAC against full CD over (N_core, N_valence) (one JSON line)")
     args = ap.parse_args()
     if args.scaling:
         print(json.dumps(scaling([60, 120, 240, 480, 960], 240)), flush=True)
+        return
+    if args.heatmap:
+        grid = [0, 2, 4, 8, 12, 16, 20]
+        print(json.dumps(heatmap(6, grid, grid, 16, 64, (200, 400))), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "

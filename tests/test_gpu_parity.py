@@ -478,6 +478,18 @@ def test_empty_inputs(lib):
     assert all(o["flags"] == 0 for o in out)
 
 
+def test_refined_set_converges_to_full_cd():
+    """CD-WAC(20, N_valence, 16) on a 64-node grid against full CD (W directly at
+    every residue, secant over cdwac_sigma_cd), two seeded systems: the error
+    does not grow as valence points are added and is below 0.05 meV with 20."""
+    import bench
+    d = bench.heatmap(2, [20], [0, 8, 20], 16, 64, (200, 260))
+    mae = d["mae_mev"][0]
+    print("MAE (meV) at N_valence 0, 8, 20:", mae)
+    assert d["states_without_root"] == [[0, 0, 0]]
+    assert mae[0] >= mae[1] >= mae[2] and mae[2] <= 0.05
+
+
 def test_skeleton_nodes_fall_back_when_excitations_exceed_the_range(lib):
     """With very strong screening the RPA excitations exceed the range the
     skeleton decomposition assumes; the range check after Pi then re-runs
