@@ -162,7 +162,7 @@ def test_deploy_naux6600_learned_seed(lib):
     product, W in the fp16 split, skeleton nodes) with and without the seed,
     against the fp16 split (FP32-level Pi) without it.  Every root has Z in
     (0.5, 1] and |f| <= 1e-8 Ha, or <= 1 meV where the seed is accepted (the
-    secant is the fallback and the judge); all states within 1 meV of the
+    secant is the fallback and decides); all states within 1 meV of the
     reference; an accepted seed ends the search after 5 self-energy
     evaluations and a rejected one costs at most one more than the plain
     search.  Sampled Pi entries against the oracle's one-by-one definition."""
