@@ -79,3 +79,15 @@ def test_refined_reference_points():
     assert len(grids.refined_refs(s.eps, s.n_occ, s.state_idx, lo, hi, 0, 0)) == 0
     with pytest.raises(ValueError):
         grids.refined_refs(s.eps, s.n_occ, s.state_idx, lo, hi, 2, 2, delta_c=0.0)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N > 1 exits with a message before touching a GPU."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
