@@ -22,6 +22,7 @@ namespace {
 // Device memory for the prescaled polarizability operands (batched over the
 // weight vectors so that large systems stay within a fixed budget).
 constexpr size_t kPrescaleBudget = (size_t)48 << 30;
+constexpr size_t kPiListPad = 8 * 128;
 
 // Fit ranges are widened by the Z-factor step of the root search so that
 // every self-energy evaluation of the solver finds a Pade model.
@@ -76,6 +77,7 @@ struct HostState {
 struct cdwac_ctx {
     int device = 0;
     int n_cu = 256;   // compute units of the device
+    std::vector<int2> pi_work[2];   // polarizability work lists of the last prepare
     hipStream_t stream = nullptr;
     std::string err;
     void* ws_user = nullptr;
@@ -449,10 +451,12 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
         P.nb = (int)std::max<size_t>(1, std::min<size_t>(P.n_f, kPrescaleBudget / (n_pl * per_f)));
         add(P, P.yh, per_f * P.nb);
         add(P, P.yl, n_pl == 2 ? per_f * P.nb : 0);
-        P.n_tpi = (int)pi_tiles(P.npad).size();
+        P.n_tpi = pi_tile_count(P.npad);
         P.n_tw = (int)w_tiles(P.npad, P.cpad).size();
         P.n_twf = (int)w_tiles(P.npad, P.cfpad).size();
-        add(P, P.t_pi, sizeof(int2) * P.n_tpi);
+        // work lists of a full batch and of the last one, each padded by at
+        // most 8 rounds of one tile per CU (up to 128 CUs per XCD)
+        add(P, P.t_pi, sizeof(int2) * 2 * ((size_t)P.nb * P.n_tpi + kPiListPad));
         add(P, P.t_w, sizeof(int2) * P.n_tw);
         add(P, P.t_wf, sizeof(int2) * P.n_twf);
     }
@@ -798,8 +802,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
         launch_scales_pi(st, amax, P.n_f, sf);
         launch_split_panel(st, et, sys->o_ia, 0, 1, P.K, P.n_aux, P.K, sf, at<uint16_t>(ctx, P.xh),
                            pi_split ? at<uint16_t>(ctx, P.xl) : nullptr, at<float>(ctx, P.x32), P.npad, P.kpad);
-        std::vector<int2> tp = pi_tiles(P.npad), tw = w_tiles(P.npad, P.cpad), twf = w_tiles(P.npad, P.cfpad);
-        TRY(upload(ctx, at<int2>(ctx, P.t_pi), tp.data(), tp.size()));
+        std::vector<int2> tw = w_tiles(P.npad, P.cpad), twf = w_tiles(P.npad, P.cfpad);
         TRY(upload(ctx, at<int2>(ctx, P.t_w), tw.data(), tw.size()));
         TRY(upload(ctx, at<int2>(ctx, P.t_wf), twf.data(), twf.size()));
     }
@@ -837,18 +840,31 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
                 per_batch = per;
             }
         }
+        // work lists of a full batch and of the last batch (kept in the context
+        // until the next prepare, as the source of the asynchronous upload)
+        const int cu_x = std::max(1, ctx->n_cu / 8);
+        const int last = n_pi16 - per_batch * ((n_pi16 - 1) / per_batch);
+        ctx->pi_work[0] = pi_worklist(P.npad, per_batch, cu_x);
+        ctx->pi_work[1] = last != per_batch ? pi_worklist(P.npad, last, cu_x) : std::vector<int2>();
+        const size_t cap = (size_t)P.nb * P.n_tpi + kPiListPad;
+        if (ctx->pi_work[0].size() > cap || ctx->pi_work[1].size() > cap)
+            return fail(ctx, CDWAC_EINVAL, "polarizability work list exceeds its buffer (more than 128 CUs per XCD)");
+        int2* wl = at<int2>(ctx, P.t_pi);
+        TRY(upload(ctx, wl, ctx->pi_work[0].data(), ctx->pi_work[0].size()));
+        TRY(upload(ctx, wl + cap, ctx->pi_work[1].data(), ctx->pi_work[1].size()));
         for (int f0 = 0; f0 < n_pi16; f0 += per_batch) {
             const int nfb = std::min(per_batch, n_pi16 - f0);
+            const int li = nfb == per_batch ? 0 : 1;
             TRY(seg_begin(ctx, 7));
             launch_prescale(st, et, at<float>(ctx, P.x32), P.npad, P.kpad, at<float>(ctx, P.cw), sf + 2, pm + f0, nfb,
                             at<uint16_t>(ctx, P.yh), pi_split ? at<uint16_t>(ctx, P.yl) : nullptr);
             LAUNCHCK();
             TRY(seg_end(ctx));
             TRY(seg_begin(ctx, 1));
-            launch_pi_gemm(st, P.prec, P.npad, P.kpad, pm + f0, nfb, at<uint16_t>(ctx, P.xh),
+            launch_pi_gemm(st, P.prec, P.npad, P.kpad, pm + f0, at<uint16_t>(ctx, P.xh),
                            at<uint16_t>(ctx, pi_split ? P.xl : P.xh), at<uint16_t>(ctx, P.yh),
-                           at<uint16_t>(ctx, pi_split ? P.yl : P.yh), at<int2>(ctx, P.t_pi), P.n_tpi, pi_unscale,
-                           at<int>(ctx, P.idflag), at<double>(ctx, P.E));
+                           at<uint16_t>(ctx, pi_split ? P.yl : P.yh), wl + li * cap, (int)ctx->pi_work[li].size(),
+                           pi_unscale, at<int>(ctx, P.idflag), at<double>(ctx, P.E));
             LAUNCHCK();
             TRY(seg_end(ctx));
         }
@@ -1433,7 +1449,7 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
            o_amax = take(sizeof(uint32_t) * (2 + 2 * (size_t)nf)), o_sf = take(sizeof(double) * (2 + 4 * (size_t)nf)),
            o_cw = take((f64 ? 8 : 4) * (size_t)nf * kpad), o_x = take(8 * (size_t)npad * kpad),
            o_y = take(f64 ? 0 : 4 * (size_t)nf * npad * kpad), o_E = take(sizeof(double) * (size_t)nf * npad * npad);
-    const std::vector<int2> tiles = f64 ? std::vector<int2>() : pi_tiles(npad);
+    const std::vector<int2> tiles = f64 ? std::vector<int2>() : pi_worklist(npad, nf, std::max(1, ctx->n_cu / 8));
     size_t o_t = take(sizeof(int2) * std::max<size_t>(1, tiles.size()));
     size_t o_map = take(sizeof(int) * nf);
     std::vector<int> fmap(nf);
@@ -1484,9 +1500,8 @@ int cdwac_polarizability(cdwac_ctx* ctx, const cdwac_system* sys, int32_t prec, 
                                kpad);
             launch_prescale(st, et, x32, npad, kpad, (float*)(buf + o_cw), sf + 2, (int*)(buf + o_map), nf, yh,
                             split ? yl : nullptr);
-            launch_pi_gemm(st, prec, npad, kpad, (int*)(buf + o_map), nf, xh, xl, yh, yl, (int2*)(buf + o_t),
-                           (int)tiles.size(),
-                           sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));
+            launch_pi_gemm(st, prec, npad, kpad, (int*)(buf + o_map), xh, xl, yh, yl, (int2*)(buf + o_t),
+                           (int)tiles.size(), sf + 2 + nf, (int*)(buf + o_id), (double*)(buf + o_E));
         }
         if (hipGetLastError() != hipSuccess) {
             rc = fail(ctx, CDWAC_EHIP, "kernel launch failed");

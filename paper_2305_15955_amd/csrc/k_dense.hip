@@ -313,23 +313,24 @@ __device__ inline int out_row(int w, int bi, int lane, int v) {
 }
 __device__ inline int out_col(int w, int bj, int lane) { return (w & 1) * 128 + bj * 32 + (lane & 31); }
 
-// eps_f = delta_f I - Pi_f for the listed tiles of the planes f = fmap[fb]
-// (B = prescaled Y_f, batch slot fb).
+// eps_f = delta_f I - Pi_f for the tiles of a work list (pi_worklist): entry
+// {fb << 16 | I, J} is tile (I, J) of plane f = fmap[fb] (B = prescaled Y_f,
+// batch slot fb); {-1, -1} is an empty slot.
 template <int ET, bool SPLIT>
 __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __restrict__ xh,
                                                           const uint16_t* __restrict__ xl,
                                                           const uint16_t* __restrict__ yh,
                                                           const uint16_t* __restrict__ yl, int64_t kpad,
-                                                          const int2* __restrict__ tiles, int n_tiles,
+                                                          const int2* __restrict__ work,
                                                           const int* __restrict__ fmap,
                                                           const double* __restrict__ pi_unscale,
                                                           const int* __restrict__ idflag, double* __restrict__ E,
                                                           int npad) {
     __shared__ uint4 lds[Ring<SPLIT>::SLOTS];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int fb = bid / n_tiles;
-    const int2 tile = tiles[bid % n_tiles];
-    const int I = tile.x, J = tile.y, f = fmap[fb];
+    const int2 e = work[bid];
+    if (e.x < 0) return;
+    const int fb = e.x >> 16, I = e.x & 0xffff, J = e.y, f = fmap[fb];
     const int64_t ao = (int64_t)I * GT * kpad;
     const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GT * kpad;
     v16f acc[2][4];
@@ -400,17 +401,46 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
 // Host side: tile lists and launchers
 // ============================================================================
 
-// Tiles (I, J), J <= I, of 256 x 256 covering the lower triangle of an
-// npad x npad matrix, in 4 x 8 blocks so that consecutive tiles share operand
-// panels.
-std::vector<int2> pi_tiles(int npad) {
-    std::vector<int2> out;
+// Number of 256 x 256 tiles (I, J), J <= I, covering the lower triangle of an
+// npad x npad matrix.
+int pi_tile_count(int npad) {
     const int n = npad / GT;
-    for (int I0 = 0; I0 < n; I0 += 4)
-        for (int J0 = 0; J0 < n; J0 += 8)
-            for (int I = I0; I < std::min(n, I0 + 4); ++I)
-                for (int J = J0; J < std::min(n, J0 + 8); ++J)
-                    if (J <= I) out.push_back(make_int2(I, J));
+    return n * (n + 1) / 2;
+}
+
+// Work list of the polarizability contraction over nfb planes, for a device
+// whose workgroups go round robin to kXcd XCDs of cu_per_xcd CUs each (one
+// 256 x 256 tile per CU at a time, so an XCD runs its tiles in rounds of
+// cu_per_xcd).  A round's tiles share operand panels in that XCD's L2:
+// * the lower triangle is cut into 4-row bands, each into 4 x 4 pieces left
+//   of its diagonal block and the diagonal triangle;
+// * the list runs piece by piece, each piece over all planes, so that a round
+//   holds the same piece of consecutive planes: one set of X row panels (the
+//   same for every plane) and the Y_f panels of a few planes;
+// * each XCD takes a contiguous run of whole rounds (entries are dealt so that
+//   XCD x runs entries x q .. x q + q - 1 in order), padded with empty slots
+//   {-1, -1} at the end of its run only, so that no round straddles a piece
+//   boundary by a shift.
+// Entries {fb << 16 | I, J}; length kXcd * q.
+std::vector<int2> pi_worklist(int npad, int nfb, int cu_per_xcd) {
+    constexpr int kXcd = 8;
+    const int n = npad / GT;
+    std::vector<int2> tiles;
+    tiles.reserve((size_t)nfb * pi_tile_count(npad));
+    for (int I0 = 0; I0 < n; I0 += 4) {
+        const int I1 = std::min(n, I0 + 4);
+        for (int c0 = 0; c0 <= I0; c0 += 4)            // c0 == I0: the diagonal triangle
+            for (int fb = 0; fb < nfb; ++fb)
+                for (int I = I0; I < I1; ++I) {
+                    const int J1 = c0 == I0 ? I + 1 : c0 + 4;
+                    for (int J = c0; J < J1; ++J) tiles.push_back(make_int2((fb << 16) | I, J));
+                }
+    }
+    const int64_t total = (int64_t)tiles.size(), per_round = std::max(cu_per_xcd, 1);
+    const int64_t q = per_round * ((total + kXcd * per_round - 1) / (kXcd * per_round));
+    std::vector<int2> out((size_t)(kXcd * q), make_int2(-1, -1));
+    for (int x = 0; x < kXcd; ++x)
+        for (int64_t i = 0; i < q && x * q + i < total; ++i) out[(size_t)(x * q + i)] = tiles[(size_t)(x * q + i)];
     return out;
 }
 
@@ -431,21 +461,21 @@ void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double*
     hipLaunchKernelGGL(k_pi_f64, dim3(T * n_f), dim3(256), 0, s, x64, kpad, cw64, idflag, E, npad, n_f);
 }
 
-void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* fmap, int nfb, const uint16_t* xh,
-                    const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* tiles, int n_tiles,
+void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* fmap, const uint16_t* xh,
+                    const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* work, int n_work,
                     const double* pi_unscale, const int* idflag, double* E) {
-    dim3 g(n_tiles * nfb), b(kGemmThreads);
+    dim3 g(n_work), b(kGemmThreads);
     if (prec == PREC_B16X3)
-        hipLaunchKernelGGL((k_pi_gemm<0, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<0, true>), g, b, 0, s, xh, xl, yh, yl, kpad, work, fmap, pi_unscale,
                            idflag, E, npad);
     else if (prec == PREC_B16)
-        hipLaunchKernelGGL((k_pi_gemm<0, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<0, false>), g, b, 0, s, xh, xl, yh, yl, kpad, work, fmap, pi_unscale,
                            idflag, E, npad);
     else if (prec == PREC_F16)
-        hipLaunchKernelGGL((k_pi_gemm<1, false>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<1, false>), g, b, 0, s, xh, xl, yh, yl, kpad, work, fmap, pi_unscale,
                            idflag, E, npad);
     else
-        hipLaunchKernelGGL((k_pi_gemm<1, true>), g, b, 0, s, xh, xl, yh, yl, kpad, tiles, n_tiles, fmap, pi_unscale,
+        hipLaunchKernelGGL((k_pi_gemm<1, true>), g, b, 0, s, xh, xl, yh, yl, kpad, work, fmap, pi_unscale,
                            idflag, E, npad);
 }
 

@@ -82,12 +82,13 @@ void launch_reduce_w(hipStream_t s, const double* partial_im, const double* part
 // k_dense.hip
 constexpr int kGemmRows = 256;   // row block of the 16-bit contraction (A operand)
 constexpr int kGemmCols = 256;   // column block (B operand rows)
-std::vector<int2> pi_tiles(int npad);
+int pi_tile_count(int npad);
+std::vector<int2> pi_worklist(int npad, int nfb, int cu_per_xcd);
 std::vector<int2> w_tiles(int npad, int cpad);
 void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double* x64, const double* cw64,
                    const int* idflag, double* E);
-void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* fmap, int nfb, const uint16_t* xh,
-                    const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* tiles, int n_tiles,
+void launch_pi_gemm(hipStream_t s, int prec, int npad, int64_t kpad, const int* fmap, const uint16_t* xh,
+                    const uint16_t* xl, const uint16_t* yh, const uint16_t* yl, const int2* work, int n_work,
                     const double* pi_unscale, const int* idflag, double* E);
 int w_partial_blocks(int prec, int npad);
 void launch_w(hipStream_t s, int prec, int npad, int f0, int nf, const double* lam64, const uint16_t* lh,
