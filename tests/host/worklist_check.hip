@@ -1,0 +1,37 @@
+// Host-side check of the polarizability work list (no GPU needed): every
+// lower-triangle tile of every plane exactly once, entries in range, the
+// padding below one round per XCD, and every XCD's run a whole number of
+// rounds.  Exit status 0 on success.
+#include "../../paper_2305_15955_amd/csrc/k_dense.hip"
+
+#include <cstdio>
+#include <set>
+
+int main() {
+    int bad = 0;
+    for (int npad : {256, 512, 768, 1280, 2560, 5120, 6656})
+        for (int nfb : {1, 2, 3, 7, 12, 16})
+            for (int cu : {1, 16, 32, 38}) {
+                const std::vector<int2> w = cdwac::pi_worklist(npad, nfb, cu);
+                const int n = npad / 256;
+                std::set<long> seen;
+                for (const int2 e : w) {
+                    if (e.x < 0) {
+                        if (e.y != -1) ++bad;
+                        continue;
+                    }
+                    const int fb = e.x >> 16, I = e.x & 0xffff, J = e.y;
+                    if (fb >= nfb || I >= n || J < 0 || J > I || !seen.insert(((long)fb * n + I) * n + J).second)
+                        ++bad;
+                }
+                const long want = (long)nfb * n * (n + 1) / 2;
+                if ((long)seen.size() != want || w.size() % 8 != 0 || (w.size() / 8) % cu != 0 ||
+                    (long)w.size() - want >= 8L * cu) {
+                    ++bad;
+                    std::printf("npad %d nfb %d cu %d: %zu entries for %ld tiles\n", npad, nfb, cu, w.size(), want);
+                }
+                if ((int)cdwac::pi_tile_count(npad) != n * (n + 1) / 2) ++bad;
+            }
+    std::printf("%s\n", bad ? "FAIL" : "ok");
+    return bad != 0;
+}
