@@ -191,8 +191,9 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 // contiguous 16-byte word per lane and a half-wave reads 512 consecutive
 // bytes (no bank conflicts).  Products hi*hi + hi*lo + lo*hi accumulate in
 // FP32 in the matrix cores over the whole contraction and are converted to
-// FP64 at the end.  Tiles come from a host-built list ordered in 4 x 8 blocks,
-// and the workgroups an XCD runs together share operand panels in its L2.
+// FP64 at the end.  The polarizability's tiles come from a host-built work
+// list (pi_worklist) in which the workgroups an XCD runs together share
+// operand panels in its L2; the W contraction's from 4 x 8 blocks.
 // ============================================================================
 
 constexpr int GT = 256, GK = 32, KGR = GK / 8;
