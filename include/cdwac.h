@@ -114,7 +114,10 @@ typedef struct {
                                   family 1/(w^2 + Omega^2) over the RPA excitation range,
                                   sup-norm error <= tol relative to each function's
                                   maximum; falls back to every node if the range check
-                                  fails); 0 uses every node.  Ignored by CDWAC_P64.  [0, 1) */
+                                  fails); 0 uses every node.  Ignored by CDWAC_P64.  [0, 1).
+                                  A tolerance at the mode's own imaginary-axis W error adds
+                                  no visible error: about 1e-6 for CDWAC_F16, 1e-8 for the
+                                  splits (measured at N_aux = 5000). */
     int32_t fit_all;           /* 1: fit W^c_nm of every m (all (n, m) pairs); 0: only the
                                   m whose residue can enter the window (Eq. ffact).  The
                                   QP results are the same; 1 is the heavier fit load.     */
