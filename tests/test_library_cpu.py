@@ -71,3 +71,16 @@ def test_freq_decomposition_interpolates_w_family():
     # a tolerance below what FP64 can certify keeps every node
     skel, rest, T = cdwac.freq_decomposition(w, lo, hi, 1e-17)
     assert len(skel) == 64 and len(rest) == 0
+
+
+def test_skeleton_tolerance_table_covers_every_mode():
+    """cdwac.SKELETON_TOL has an entry for every precision mode: 0 (every node)
+    for the FP64 path, and a tolerance no looser for the split modes than for
+    the one-product modes (the splits leave less W error to hide it under)."""
+    from paper_2305_15955_amd import cdwac
+    assert set(cdwac.SKELETON_TOL) == set(cdwac.PREC)
+    assert cdwac.SKELETON_TOL["p64"] == 0.0
+    for k, v in cdwac.SKELETON_TOL.items():
+        assert 0.0 <= v < 1.0, k
+    assert cdwac.SKELETON_TOL["f16x3"] <= cdwac.SKELETON_TOL["f16"]
+    assert cdwac.SKELETON_TOL["b16x3"] <= cdwac.SKELETON_TOL["b16"]
