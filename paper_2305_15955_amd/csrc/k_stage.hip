@@ -190,15 +190,19 @@ __global__ void k_split_panel(const double* __restrict__ src, int64_t sstride, i
                               uint16_t* __restrict__ lo, float* __restrict__ f32, int rpad, int64_t cpad) {
     const int z = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int64_t kw = cpad / 8, nw = (int64_t)(rpad / 64) * kw;
+    // a wave covers 16 rows x 4 k-groups of one 64-row block: 4 lanes per row,
+    // so each row is read (and its FP32 copy written) in 256-byte runs
+    const int64_t kw = cpad / 8, ks = cpad / 32, nw = (int64_t)(rpad / 64) * ks * 4;
     const double s = scale ? scale[z] : 1.0;
     const double* sp = src + z * sstride;
     uint4* oh = reinterpret_cast<uint4*>(hi + (int64_t)z * rpad * cpad);
     uint4* ol = lo ? reinterpret_cast<uint4*>(lo + (int64_t)z * rpad * cpad) : nullptr;
     const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; w < nw; w += wstride) {
-        const int64_t rb = w / kw, g = w % kw;
-        const int64_t p = rb * 64 + lane, k0 = g * 8;
+        const int64_t rb = w / (ks * 4), rem = w % (ks * 4);
+        const int row = (int)(rem & 3) * 16 + (lane >> 2);
+        const int64_t g = (rem >> 2) * 4 + (lane & 3);
+        const int64_t p = rb * 64 + row, k0 = g * 8;
         double v[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e)
@@ -218,8 +222,9 @@ __global__ void k_split_panel(const double* __restrict__ src, int64_t sstride, i
             h[e] = ha | ((uint32_t)hb << 16);
             l[e] = la | ((uint32_t)lb << 16);
         }
-        oh[w * 64 + lane] = make_uint4(h[0], h[1], h[2], h[3]);
-        if (lo) ol[w * 64 + lane] = make_uint4(l[0], l[1], l[2], l[3]);
+        const int64_t word = (rb * kw + g) * 64 + row;
+        oh[word] = make_uint4(h[0], h[1], h[2], h[3]);
+        if (lo) ol[word] = make_uint4(l[0], l[1], l[2], l[3]);
     }
 }
 
@@ -460,7 +465,7 @@ void launch_pad_f64(hipStream_t s, const double* src, int64_t lds, int rows, int
 void launch_split_panel(hipStream_t s, int et, const double* src, int64_t sstride, int nz, int64_t lds, int rows,
                         int64_t cols, const double* scale, uint16_t* hi, uint16_t* lo, float* f32, int rpad,
                         int64_t cpad) {
-    const int64_t waves = (int64_t)(rpad / 64) * (cpad / 8);
+    const int64_t waves = (int64_t)(rpad / 64) * (cpad / 32) * 4;
     dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 4096)), nz);
     if (et == 1)
         hipLaunchKernelGGL(k_split_panel<1>, grid, dim3(256), 0, s, src, sstride, lds, rows, cols, scale, hi, lo,
