@@ -4,8 +4,7 @@ Follows Panades-Barrueta & Golze, "Accelerating core-level GW calculations by
 combining the contour deformation approach with the analytic continuation of
 W" (JCTC 2023).  Units: Hartree.  Orbitals are real, so O^{mn}_P = O^{nm}_P.
 
-Readings of passages the paper leaves open (each is also listed in the design
-notes of the repository):
+Readings of passages the paper leaves open:
 
 * spin: closed shell, the spin sum of the Adler-Wiser expression (Eq. aw)
   becomes a factor ``spin`` = 2 in Pi;
