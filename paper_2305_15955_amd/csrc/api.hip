@@ -818,28 +818,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     } else {
         const int* pm = at<int>(ctx, P.pmap);
         const int n_pi16 = P.nr64 ? P.n_imp : P.n_f;   // planes on the 16-bit path
-        // Batches of near-equal size within the Y buffers.  Every tile keeps one
-        // CU busy for the same time, so a launch takes ceil(tiles / CUs) waves
-        // of workgroups; take the split with the fewest waves in total (a last
-        // wave that is mostly empty costs as much as a full one), then the
-        // fewest launches.
-        const int min_batches = (n_pi16 + P.nb - 1) / P.nb;
-        auto waves = [&](int per) {
-            int64_t w = 0;
-            for (int f0 = 0; f0 < n_pi16; f0 += per)
-                w += ((int64_t)std::min(per, n_pi16 - f0) * P.n_tpi + ctx->n_cu - 1) / ctx->n_cu;
-            return w;
-        };
-        int per_batch = std::max(1, (n_pi16 + std::max(min_batches, 1) - 1) / std::max(min_batches, 1));
-        int64_t best = waves(per_batch);
-        for (int nbat = min_batches + 1; nbat <= std::min(n_pi16, min_batches + 4); ++nbat) {
-            const int per = (n_pi16 + nbat - 1) / nbat;
-            const int64_t w = waves(per);
-            if (w < best) {
-                best = w;
-                per_batch = per;
-            }
-        }
+        const int per_batch = pi_batch_size(n_pi16, P.nb, P.n_tpi, ctx->n_cu);
         // work lists of a full batch and of the last batch (kept in the context
         // until the next prepare, as the source of the asynchronous upload)
         const int cu_x = std::max(1, ctx->n_cu / 8);

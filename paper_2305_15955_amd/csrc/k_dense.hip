@@ -409,6 +409,36 @@ int pi_tile_count(int npad) {
     return n * (n + 1) / 2;
 }
 
+// Planes per polarizability launch for n_planes planes, at most nb per batch
+// (the Y buffers), n_tiles tiles per plane on n_cu CUs.  Batches are of
+// near-equal size.  Every tile keeps one CU busy for the same time, so a launch
+// takes ceil(tiles / CUs) waves of workgroups; the split with the fewest waves
+// in total wins (a last wave that is mostly empty costs as much as a full
+// one), then the one with the fewest launches.
+int pi_batch_size(int n_planes, int nb, int n_tiles, int n_cu) {
+    if (n_planes <= 0) return 1;
+    nb = std::max(nb, 1);
+    n_cu = std::max(n_cu, 1);
+    const int min_batches = (n_planes + nb - 1) / nb;
+    auto waves = [&](int per) {
+        int64_t w = 0;
+        for (int f0 = 0; f0 < n_planes; f0 += per)
+            w += ((int64_t)std::min(per, n_planes - f0) * n_tiles + n_cu - 1) / n_cu;
+        return w;
+    };
+    int best_per = (n_planes + min_batches - 1) / min_batches;
+    int64_t best = waves(best_per);
+    for (int nbat = min_batches + 1; nbat <= std::min(n_planes, min_batches + 4); ++nbat) {
+        const int per = (n_planes + nbat - 1) / nbat;
+        const int64_t w = waves(per);
+        if (w < best) {
+            best = w;
+            best_per = per;
+        }
+    }
+    return best_per;
+}
+
 // Work list of the polarizability contraction over nfb planes, for a device
 // whose workgroups go round robin to kXcd XCDs of cu_per_xcd CUs each (one
 // 256 x 256 tile per CU at a time, so an XCD runs its tiles in rounds of

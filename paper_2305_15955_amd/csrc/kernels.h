@@ -83,6 +83,7 @@ void launch_reduce_w(hipStream_t s, const double* partial_im, const double* part
 constexpr int kGemmRows = 256;   // row block of the 16-bit contraction (A operand)
 constexpr int kGemmCols = 256;   // column block (B operand rows)
 int pi_tile_count(int npad);
+int pi_batch_size(int n_planes, int nb, int n_tiles, int n_cu);
 std::vector<int2> pi_worklist(int npad, int nfb, int cu_per_xcd);
 std::vector<int2> w_tiles(int npad, int cpad);
 void launch_pi_f64(hipStream_t s, int npad, int64_t kpad, int n_f, const double* x64, const double* cw64,

@@ -1,7 +1,8 @@
-// Host-side check of the polarizability work list (no GPU needed): every
-// lower-triangle tile of every plane exactly once, entries in range, the
-// padding below one round per XCD, and every XCD's run a whole number of
-// rounds.  Exit status 0 on success.
+// Host-side check of the polarizability work list and batch sizes (no GPU
+// needed): every lower-triangle tile of every plane exactly once, entries in
+// range, the padding below one round per XCD, every XCD's run a whole number
+// of rounds; batches within the buffer and taking no more waves than the
+// fewest batches.  Exit status 0 on success.
 #include "../../paper_2305_15955_amd/csrc/k_dense.hip"
 
 #include <cstdio>
@@ -32,6 +33,26 @@ int main() {
                 }
                 if ((int)cdwac::pi_tile_count(npad) != n * (n + 1) / 2) ++bad;
             }
+    // batch sizes: within the buffer, near-equal batches, never more waves of
+    // workgroups than the fewest batches would take; 48 planes of 210 tiles on
+    // 256 CUs split 4 x 12 (40 waves), not 3 x 16 (42)
+    for (int np : {1, 7, 24, 48, 60, 88})
+        for (int nb : {1, 5, 16, 100})
+            for (int cu : {1, 256}) {
+                const int per = cdwac::pi_batch_size(np, nb, 210, cu);
+                const int minb = (np + nb - 1) / nb;
+                const int per0 = (np + minb - 1) / minb;
+                auto waves = [&](int p) {
+                    long w = 0;
+                    for (int f0 = 0; f0 < np; f0 += p) w += ((long)std::min(p, np - f0) * 210 + cu - 1) / cu;
+                    return w;
+                };
+                if (per < 1 || per > nb || per > np || waves(per) > waves(per0)) {
+                    ++bad;
+                    std::printf("batch np %d nb %d cu %d -> %d\n", np, nb, cu, per);
+                }
+            }
+    if (cdwac::pi_batch_size(48, 16, 210, 256) != 12) ++bad;
     std::printf("%s\n", bad ? "FAIL" : "ok");
     return bad != 0;
 }
