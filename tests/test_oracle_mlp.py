@@ -63,3 +63,28 @@ def test_adam_minimises_quadratic():
     for t in range(1, 3001):
         M.adam_step(theta, 2 * theta, m, v, t, lr=0.01)
     assert np.max(np.abs(theta)) < 1e-2
+
+
+def test_forward_hand_evaluated_network():
+    """A network with non-zero weights whose pre-activations are logarithms:
+    tanh(ln a) = (a^2 - 1) / (a^2 + 1), so every hidden value and the output
+    are known fractions.  A missing or misplaced tanh, a transposed weight
+    matrix or a dropped bias changes the output."""
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(M.N_IN)
+    a1 = rng.choice([2.0, 3.0, 0.5, 1.5, 4.0, 0.25], M.N_H1)
+    a2 = rng.choice([2.0, 3.0, 0.5, 1.5, 4.0, 0.25], M.N_H2)
+    h1 = (a1 ** 2 - 1.0) / (a1 ** 2 + 1.0)
+    h2 = (a2 ** 2 - 1.0) / (a2 ** 2 + 1.0)
+    w1 = rng.standard_normal((M.N_H1, M.N_IN))
+    w2 = 0.3 * rng.standard_normal((M.N_H2, M.N_H1))
+    w3 = rng.standard_normal((1, M.N_H2))
+    b1 = np.log(a1) - w1 @ x           # first pre-activations = ln a1
+    b2 = np.log(a2) - w2 @ h1          # second pre-activations = ln a2
+    b3 = np.array([0.25])
+    theta = np.concatenate([w1.ravel(), b1, w2.ravel(), b2, w3.ravel(), b3])
+    y, (g1, g2) = M.forward(theta, np.stack([x, x, x]))
+    np.testing.assert_allclose(g1, np.broadcast_to(h1, g1.shape), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(g2, np.broadcast_to(h2, g2.shape), rtol=0, atol=1e-13)
+    expect = float(w3[0] @ h2) + 0.25
+    np.testing.assert_allclose(y, [expect] * 3, rtol=1e-13, atol=1e-13)

@@ -34,6 +34,60 @@ def test_exchange_four_index_bruteforce():
         assert R.exchange(o, s.n_occ) == pytest.approx(total, rel=1e-14)
 
 
+def test_exchange_equals_real_space_exchange_operator():
+    """Sigma^x_n = -<n|K|n> (Eq. exs) with the exchange operator of the
+    occupied density matrix, written on a grid: <n|K|n> = sum_rs phi_n(r)
+    rho(r, s) v(r, s) phi_n(s), rho(r, s) = sum_i^occ phi_i(r) phi_i(s).  The RI
+    coefficients come from the same grid, O^{nm}_P = sum_r phi_n(r) phi_m(r)
+    L_rP with v = L L^T, so that (nm|kl) = sum_P O^{nm}_P O^{kl}_P (Eq.
+    workriv).  The real-space route shares no step with the RI sum: a sum over
+    virtual orbitals, the diagonal O^{nn} in place of O^{ni}, or a transposed
+    coefficient array gives another number."""
+    rng = np.random.default_rng(4)
+    g, n_mo, n_occ = 25, 9, 4
+    phi = np.linalg.qr(rng.standard_normal((g, n_mo)))[0]          # orthonormal on the grid
+    r = rng.uniform(0.0, 3.0, (g, 3))
+    d2 = np.sum((r[:, None, :] - r[None, :, :]) ** 2, axis=-1)
+    v = np.exp(-0.5 * d2) + 0.1 * np.eye(g)                        # positive definite kernel
+    chol = np.linalg.cholesky(v)
+    o = np.einsum("rn,rm,rp->nmp", phi, phi, chol)                   # O^{nm}_P
+    rho = phi[:, :n_occ] @ phi[:, :n_occ].T
+    for n in range(n_mo):
+        k_nn = phi[:, n] @ (rho * v) @ phi[:, n]
+        assert R.exchange(o[n].T, n_occ) == pytest.approx(-k_nn, rel=1e-12)
+
+
+def test_full_cd_sigma_with_exchange_and_given_vxc():
+    """The whole self-energy, not only its correlation part (Eq. cdselfe),
+    with a v^xc that does not cancel Sigma^x in the QP equation (Eq. qp_eq).
+    One doubly occupied orbital: its exchange with itself is -(00|00) =
+    -(O^{00})^2, here -0.4^2 (the textbook closed-shell result); the
+    correlation part is the pole form of Eq. (sigma_pole)."""
+    from scipy.optimize import brentq
+    s = one_transition(x=0.3, o_nn=0.4)
+    sigma_x = -0.4 ** 2
+    vxc = -0.3
+    freq, wts = grids.gauss_legendre_imag(200)
+    lo, hi = np.array([-12.0]), np.array([-8.0])
+    fc = R.FullCdOracle(s, freq, wts, lo, hi, eta=1e-7, vxc=[vxc])
+    poles = R.rpa_poles(s)
+    for om in (-11.0, -10.3, -9.7, -8.9):
+        assert fc.sigma(0, om) == pytest.approx(sigma_x + R.sigma_c_poles(s, 0, om, poles),
+                                                rel=1e-8, abs=1e-12)
+    # the root between the occupied pole at eps_0 - Omega and the virtual one
+    # at eps_1 + Omega, found by bracketing
+    om_rpa = float(poles[0][0])
+    f = lambda w: w - s.eps[0] - (sigma_x + R.sigma_c_poles(s, 0, w, poles)) + vxc
+    root = brentq(f, s.eps[0] - om_rpa + 1e-6, s.eps[1] + om_rpa - 1e-6, xtol=1e-14)
+    qp, z, _, flags = fc.solve(0)
+    assert flags & R.FLAG_NOROOT == 0
+    assert qp == pytest.approx(root, abs=1e-8)
+    # with v^xc = Sigma^x the root moves by about Sigma^x - v^xc = 0.14 Ha
+    g = lambda w: w - s.eps[0] - R.sigma_c_poles(s, 0, w, poles)
+    root_hf = brentq(g, s.eps[0] - om_rpa + 1e-6, s.eps[1] + om_rpa - 1e-6, xtol=1e-14)
+    assert abs(root - root_hf) > 0.1
+
+
 # ---------------------------------------------------------- polarizability
 
 def test_polarizability_bruteforce_two_fractions():
@@ -179,6 +233,66 @@ def test_thiele_even_length_vanishes_at_infinity():
         assert abs(R.thiele_eval(coef, nodes, big)[0]) < 1e-10
     coef, nodes = R.thiele_greedy(u[:3], w[:3], tol=0.0)
     assert abs(R.thiele_eval(coef, nodes, np.array([-1e14 + 0j]))[0]) > 1e-6
+
+
+def test_thiele_greedy_order_by_hand():
+    """The greedy order of Sec. 3.2 as read here: first the point of largest
+    |W|; then, each time, the point where the current convergent has the
+    largest L1 error |Re(W - T)| + |Im(W - T)|, lowest index on ties.  The
+    convergents are worked out by hand: after one term T = W_1; after two,
+    T = a_1 / (1 + a_2 (u - u_1)) has 1/T linear in u through both points.
+    The data are built so that the modulus of the error, or the smallest
+    error, would pick other points in both rounds, and so that a convergent
+    that is not updated would pick another third point."""
+    u = np.array([-1.0, -4.0, -0.25, 0.5 + 0.01j, 2.0 + 0.02j, -9.0])
+    # W_0 = 1 and W_1 = 1/(1 + i): 1/T2 is linear in u from 1 at u_0 = -1 to 1 + i at u_1 = -4
+    t2 = lambda x: 1.0 / (1.0 - 1j * (x + 1.0) / 3.0)
+    w = np.array([1.0, 0.5 - 0.5j, 0.1, 0.95, 0.3 + 0.2j, t2(-9.0) + 0.55 + 0.55j])
+    assert t2(-9.0) == pytest.approx((9.0 - 24.0j) / 73.0, abs=1e-15)
+    assert 1.0 / w[1] == pytest.approx(1.0 + 1.0j)
+    l1 = lambda r: np.abs(r.real) + np.abs(r.imag)
+    # round 2 (T = W_0 = 1): L1 picks 1, the modulus would pick 2, the minimum 3
+    rest = [1, 2, 3, 4, 5]
+    r = w[rest] - 1.0
+    assert rest[int(np.argmax(l1(r)))] == 1
+    assert rest[int(np.argmax(np.abs(r)))] == 2 and rest[int(np.argmin(l1(r)))] == 3
+    # round 3 (T = t2): L1 picks 5, the modulus 2; an un-updated T = 1 would pick 2
+    rest = [2, 3, 4, 5]
+    r = w[rest] - t2(u[rest])
+    assert rest[int(np.argmax(l1(r)))] == 5
+    assert rest[int(np.argmax(np.abs(r)))] == 2
+    assert rest[int(np.argmax(l1(w[rest] - 1.0)))] == 2
+    coef, nodes = R.thiele_greedy(u, w, tol=0.0)
+    np.testing.assert_array_equal(nodes[:3], u[[0, 1, 5]])
+    # the two-term convergent itself: T(u) = a_1 / (1 + a_2 (u - u_1))
+    np.testing.assert_allclose(R.thiele_eval(coef[:2], nodes[:2], u), t2(u), rtol=1e-14)
+    # a tie in the L1 error goes to the lowest index
+    ut = np.array([-1.0, -4.0, -0.25, -9.0])
+    for wt, second in ((np.array([1.0, 0.5 - 0.5j, 0.5 + 0.5j, 0.2]), 1),
+                       (np.array([1.0, 0.2, 0.5 + 0.5j, 0.5 - 0.5j]), 2)):
+        _, nd = R.thiele_greedy(ut, wt, tol=0.0)
+        assert nd[1] == ut[second]
+
+
+def test_spectral_function_constant_sigma_is_a_unit_lorentzian():
+    """With a constant complex self-energy Sigma = s_r + i s_i the diagonal
+    spectral function (Sec. 5.5) is a Lorentzian centred at
+    eps_n + s_r - v^xc with half width |s_i|: area 1, height 1/(pi |s_i|) at
+    the centre and half of it one half width away."""
+    from scipy import integrate
+    e_n, vxc = -10.3, -0.4
+    for sig in (0.2 - 0.05j, -0.7 + 0.01j):
+        centre = e_n + sig.real - vxc
+        gam = abs(sig.imag)
+        a = lambda x: R.spectral_function(x, e_n, sig, vxc)
+        area = (integrate.quad(a, -np.inf, centre, epsabs=1e-13, epsrel=1e-12, limit=200)[0]
+                + integrate.quad(a, centre, np.inf, epsabs=1e-13, epsrel=1e-12, limit=200)[0])
+        assert area == pytest.approx(1.0, abs=1e-9)
+        assert a(centre) == pytest.approx(1.0 / (math.pi * gam), rel=1e-13)
+        assert a(centre + gam) == pytest.approx(0.5 / (math.pi * gam), rel=1e-12)
+        assert a(centre - gam) == pytest.approx(0.5 / (math.pi * gam), rel=1e-12)
+        xs = np.linspace(centre - 5 * gam, centre + 5 * gam, 2001)
+        assert xs[int(np.argmax([a(x) for x in xs]))] == pytest.approx(centre, abs=1e-12 + 10 * gam / 2000)
 
 
 def mp_thiele_natural(u, w):
