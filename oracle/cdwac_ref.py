@@ -422,6 +422,10 @@ class CdwacOracle:
         coef, nodes = self.fits[s][m]
         return complex(thiele_eval(coef, nodes, np.array([z * z]))[0])
 
+    def w_residue(self, s: int, m: int, z: complex) -> complex:
+        """W^c_nm at a residue point of Eq. (Rn_term): the Pade model."""
+        return self.w_model(s, m, z)
+
     def sigma(self, s: int, omega: float) -> float:
         """Re Sigma_n(omega) = Sigma^x + Re R - I (Eq. cdselfe), CD-WAC."""
         i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
@@ -454,6 +458,39 @@ class CdwacOracle:
     def solve_all(self, tol: float = 1e-10, maxit: int = 100):
         return [self.solve(s, tol, maxit) for s in range(self.sys.n_states)]
 
+    # -- G_{Delta H} W_0 (Sec. 4) ------------------------------------------
+    def sigma_g_shifted(self, s: int, omega: float, dh: float) -> float:
+        """Re Sigma_n(omega) with a shift dh in the denominator of G: every
+        energy of G and the Fermi level moved by dh (W and its models stay)."""
+        eps_g = self.eps_g + dh
+        ef = self.eps_f + dh
+        i_term = integral_term(omega, eps_g, self.w_im[s], self.freq, self.weight)
+        r_term = residue_term(omega, eps_g, ef, self.eta, lambda m, z: self.w_residue(s, m, z))
+        return self.sigma_x[s] + r_term - i_term
+
+    def hedin_shift(self, s: int) -> float:
+        """Delta H_n, fixed before the QP iteration: the first-order G0W0
+        correction at the Kohn-Sham energy, Re Sigma_n(eps_n) - v^xc_n (the
+        paper names the shift and where it enters, not its recipe; this
+        moves G's pole of state n to the linearised G0W0 energy)."""
+        n = int(self.sys.state_idx[s])
+        return self.sigma(s, float(self.eps_qp[n])) - float(self.vxc[s])
+
+    def solve_hedin(self, s: int, tol: float = 1e-10, maxit: int = 100):
+        """QP root of Eq. (qp_eq) with the self-energy of the shifted G.
+        Every model m must exist, so the oracle must be built with fit_all
+        (the shifted residues |eps_m + dh - omega| reach beyond the window's
+        fit range).  Returns (qp, z, n_evals, flags, dh)."""
+        if not self.fit_all and not isinstance(self, FullCdOracle):
+            raise ValueError("solve_hedin needs an oracle built with fit_all=True")
+        dh = self.hedin_shift(s)
+        n = int(self.sys.state_idx[s])
+        e_n = float(self.eps_qp[n])
+        vxc = float(self.vxc[s])
+        r = qp_solve(lambda x: x - e_n - self.sigma_g_shifted(s, x, dh) + vxc, e_n,
+                     float(self.win_lo[s]), float(self.win_hi[s]), tol, maxit)
+        return (*r, dh)
+
 
 class FullCdOracle(CdwacOracle):
     """Full contour deformation (Sec. 3.4, CD branch): W at every residue.
@@ -469,6 +506,10 @@ class FullCdOracle(CdwacOracle):
                          win_lo, win_hi, eta=eta, eta_ref=eta, pade_tol=0.0,
                          vxc=vxc, eps_fermi=eps_fermi, fit_all=True, eps_qp=eps_qp)
         self._cache = {}
+
+    def w_residue(self, s: int, m: int, z: complex) -> complex:
+        """W^c_nm at a residue point: evaluated directly (full CD)."""
+        return self.w_direct(s, m, z)
 
     def w_direct(self, s: int, m: int, z: complex) -> complex:
         key = (s, complex(z))

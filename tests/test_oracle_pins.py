@@ -398,6 +398,42 @@ def test_moved_g_energies_full_cd_equals_pole_sum():
     assert n_res[0] == pytest.approx(R.qp_solve(f, s.eps[0], lo[0], hi[0])[0], abs=1e-7)
 
 
+def test_hedin_shifted_g_full_cd_equals_pole_sum():
+    """G_{Delta H} W_0 (Sec. 4): a shift Delta H_n in the denominator of G,
+    fixed before the QP iteration.  On the 60-orbital core case with W
+    evaluated directly at every residue (full CD):
+    * Delta H_n = Re Sigma_n(eps_n) - v^xc_n equals the pole form of
+      Eq. (sigma_pole) at eps_n (v^xc = Sigma^x here, so it is Sigma^c);
+    * the self-energy of the shifted G equals the pole form with every pole
+      of G and the Fermi level moved by Delta H_n and W's poles unchanged,
+      away from the state's own shifted pole.
+    The root itself is not pinned here: the shift puts state n's own G pole
+    within ~1 meV of its QP energy, where the residue term switches W_nn off
+    (Eq. ffact) and the imaginary-axis quadrature of I_n, whose smallest node
+    is ~1e-4 Ha, cannot follow; the quadrature's self-energy has a step there
+    that the pole form does not (they differ by 12 meV in the root)."""
+    import dataclasses
+    s, freq, wts, _, _, lo, hi = cfg1_inputs()
+    freq, wts = grids.gauss_legendre_imag(100)
+    fc = R.FullCdOracle(s, freq, wts, lo, hi, eta=1e-5)
+    poles = R.rpa_poles(s)
+    e_n = float(s.eps[0])
+    dh = R.sigma_c_poles(s, 0, e_n, poles)
+    assert fc.hedin_shift(0) == pytest.approx(dh, rel=1e-6)
+    assert abs(dh) > 1e-3                         # the core level moves by eV
+    sys_g = dataclasses.replace(s, eps=s.eps + dh)
+    ef_g = R.fermi_level(s.eps, s.n_occ) + dh
+    for om_ev in (-300.0, -292.0, -283.0, -275.0):
+        om = om_ev / synth.HARTREE_EV
+        got = fc.sigma_g_shifted(0, om, dh) - fc.sigma_x[0]
+        assert got == pytest.approx(R.sigma_c_poles(sys_g, 0, om, poles, eps_fermi=ef_g), rel=1e-6, abs=1e-9)
+    qp, z, _, flags, dh2 = fc.solve_hedin(0)
+    assert dh2 == fc.hedin_shift(0) and flags & R.FLAG_NOROOT == 0
+    # the shifted G moves the root away from G0W0's, towards its own pole
+    assert abs(qp - fc.solve(0)[0]) > 1e-3
+    assert abs(qp - (e_n + dh)) < 1e-3
+
+
 def test_evgw_loop_on_the_pole_form():
     """The eigenvalue loop feeds each solve's QP energies back into G (evGW0)
     or into G and W (evGW).  On a single transition with W and G from the pole
