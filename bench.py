@@ -8,12 +8,17 @@ every core state.  Inputs (KS energies, RI coefficients) are seeded synthetic
 arrays already resident in HBM when the timed region starts.
 
 Prints one JSON line.  value = core QP energies per second of the whole job
-(fp16 polarizability, fp16-split W, FP64 elsewhere, skeleton imaginary
-nodes, learned seed if a model is installed);
-also reported: the plain FP64 GPU path, the per-state error of the reduced
-path against it in meV, per-stage times from HIP events on the library's
-stream, the roofline of the polarizability kernel, and the FP64 oracle timed
-on a bounded sample of the same workload on the host CPU.
+at the stated configuration: Pi and W contracted on the matrix cores in the
+bf16 hi/lo split (three products, FP32 accumulation), the dielectric
+inversion, Pade fits, self-energy and root search in FP64, Pi, eps^-1 and W
+at every one of the 64 imaginary Gauss-Legendre nodes and at every near-real
+Pade reference, and the learned seed if a model is installed.
+Also reported: the plain FP64 GPU path (warm, timed over several steps), the
+per-state error of the reduced path against it in meV, per-stage times from
+HIP events on the library's stream, the roofline of the polarizability
+kernel, faster variants of the method under their own key (never as value),
+and the FP64 oracle timed on a bounded sample of the same workload on the
+host CPU.
 """
 from __future__ import annotations
 
@@ -31,7 +36,9 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f16": 2.5e15, "f16x3": 2.5e15, "b16x3": 2.5e15, "b16": 2.5e15, "p64": 78.6e12}   # dense MFMA, FLOP/s
 PRODUCTS = {"f16": 1, "f16x3": 3, "b16x3": 3, "b16": 1, "p64": 1}      # matrix-core products per MAC of Pi
-DTYPE = {"f16": "f16 (Pi) + f16x3 (W) + f64", "f16x3": "f16x3 + f64", "b16x3": "bf16x3 + f64",
+DTYPE = {"f16": "f16 (Pi, one product) + f16x3 (W) + f64",
+         "f16x3": "f16x3 (fp16 hi/lo split, in place of FP32) + f64",
+         "b16x3": "bf16x3 (bf16 hi/lo split, FP32 accumulation) + f64",
          "b16": "bf16 + f64", "p64": "f64"}
 MODEL_PATH = os.path.join(ROOT, "paper_2305_15955_amd", "seed_model.npz")
 
@@ -42,11 +49,12 @@ def log(*a):
 
 def measured_traffic(prec, workload, launches, planes):
     """HBM bytes per k_pi_gemm launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a 1 GiB copy), or None if
-    the summary is for another kernel source, launch count or plane count."""
+    summary of this precision mode and workload (FETCH_SIZE + WRITE_SIZE,
+    calibrated on a 1 GiB copy), or None if there is none, or if it is for
+    another kernel source, launch count or plane count."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_pi_gemm_{workload}_hbm_traffic.md")
-    if prec != "f16" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"k_pi_gemm_{prec}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
@@ -148,11 +156,12 @@ def build_inputs(name):
     return spec, s, freq, wts, ref_im, ref_re, lo, hi
 
 
-def cpu_baseline(s, freq, n_re, n_states):
-    """The oracle's wmatrix at one imaginary node, full size, timed; scaled to
-    QP energies per second: the oracle's prepare runs n_freq such real
-    evaluations and n_re complex ones (4x the real flops), its QP loop is
-    negligible next to them."""
+def cpu_baseline(s, freq, ref_re, n_states):
+    """The oracle's wmatrix (Pi, Lambda, W of every state) at full size, timed
+    at one imaginary node and at one near-real reference point; scaled to QP
+    energies per second: the oracle's preparation runs n_freq real and n_re
+    complex such evaluations, and its fits and QP loop are negligible next to
+    them (timed on the 60-orbital case: well under a second)."""
     from oracle import cdwac_ref as R
     try:
         from threadpoolctl import threadpool_info
@@ -160,20 +169,26 @@ def cpu_baseline(s, freq, n_re, n_states):
                        if i.get("user_api") == "blas"] or [os.cpu_count() or 1])
     except Exception:
         threads = os.cpu_count() or 1
-    w = float(freq[len(freq) // 2])
-    t0 = time.perf_counter()
-    pi = R.polarizability(s.o_ia, s.eps, s.n_occ, 1j * w, s.spin)
-    lam = R.lambda_matrix(pi)
-    del pi
-    for st in range(n_states):
-        R.w_elements(s.o_nm[st], lam)
-    dt = time.perf_counter() - t0
-    t_job = dt * (len(freq) + 4 * n_re)
+
+    def one(z):
+        t0 = time.perf_counter()
+        pi = R.polarizability(s.o_ia, s.eps, s.n_occ, z, s.spin)
+        lam = R.lambda_matrix(pi)
+        del pi
+        for st in range(n_states):
+            R.w_elements(s.o_nm[st], lam)
+        return time.perf_counter() - t0
+    t_re = one(1j * float(freq[len(freq) // 2]))
+    log(f"cpu baseline: real node {t_re:.1f} s")
+    t_cx = one(complex(float(ref_re[len(ref_re) // 2]), 1e-3))
+    log(f"cpu baseline: complex node {t_cx:.1f} s")
+    t_job = t_re * len(freq) + t_cx * len(ref_re)
     return {"value": n_states / t_job, "unit": "core QP energies/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": (f"oracle wmatrix (Pi, Lambda, W for {n_states} states) at 1 of {len(freq)} "
-                       f"imaginary nodes, full size, {dt:.1f} s; job time scaled as "
-                       f"{len(freq)} real + {n_re} complex (4x) nodes = {t_job:.0f} s")}
+            "sample": (f"oracle wmatrix (Pi, Lambda, W for {n_states} states) at full size, timed at one of "
+                       f"{len(freq)} imaginary nodes ({t_re:.1f} s) and one of {len(ref_re)} near-real "
+                       f"points ({t_cx:.1f} s); job time {len(freq)} x {t_re:.1f} + {len(ref_re)} x "
+                       f"{t_cx:.1f} = {t_job:.0f} s")}
 
 
 def scaling(sizes, cd_qp_max):
@@ -258,11 +273,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="precision_naux5000")
-    ap.add_argument("--prec", default="f16", choices=["f16", "f16x3", "b16x3", "b16", "p64"])
-    ap.add_argument("--fp64-steps", type=int, default=1, help="timed steps of the FP64 GPU path")
-    ap.add_argument("--rank-tol", type=float, default=None,
-                    help="imaginary-node decomposition tolerance of the 16-bit path (0: every node; "
-                         "default: the mode's entry of cdwac.SKELETON_TOL)")
+    ap.add_argument("--prec", default="b16x3", choices=["f16", "f16x3", "b16x3", "b16", "p64"])
+    ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the FP64 GPU path")
+    ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed steps of the FP64 GPU path")
+    ap.add_argument("--rank-tol", type=float, default=0.0,
+                    help="imaginary-node decomposition tolerance of the 16-bit path (0, the default: Pi, "
+                         "eps^-1 and W at every node)")
+    ap.add_argument("--variant-steps", type=int, default=3,
+                    help="timed steps of each faster variant reported under 'variants' (0: none)")
     ap.add_argument("--near-real-f64", action="store_true",
                     help="16-bit modes: Pi at the near-real reference points on the FP64 path")
     ap.add_argument("--no-mlp", action="store_true")
@@ -289,8 +307,6 @@ def main():
     import torch
     from paper_2305_15955_amd import cdwac, synth
 
-    if args.rank_tol is None:
-        args.rank_tol = cdwac.SKELETON_TOL[args.prec]
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
     spec, s, freq, wts, ref_im, ref_re, lo, hi = build_inputs(args.workload)
@@ -306,17 +322,18 @@ def main():
         m = np.load(MODEL_PATH)
         lib.cdwac_mlp_set_model(m["theta"], m["mu"], m["sd"], float(m["out_mu"]), float(m["out_sd"]))
 
-    def params(prec, mlp):
+    def params(prec, mlp, rank_tol=None):
+        rank_tol = args.rank_tol if rank_tol is None else rank_tol
         return lib.make_params(freq, wts, ref_im, ref_re, lo, hi, prec=prec,
                                pade_tol=1e-9, use_mlp_seed=mlp, mlp_accept=1e-4 / synth.HARTREE_EV,
-                               freq_rank_tol=args.rank_tol if prec != "p64" else 0.0,
+                               freq_rank_tol=rank_tol if prec != "p64" else 0.0,
                                near_real_f64=args.near_real_f64 and prec != "p64")
 
     sysc, keep = lib.make_system(s, o_ia_dev=o_ia, o_nm_dev=o_nm)
     lib.cdwac_set_timing(True)
 
-    def run_steps(prec, mlp, warmup, steps):
-        prm, arrs = params(prec, mlp)
+    def run_steps(prec, mlp, warmup, steps, rank_tol=None):
+        prm, arrs = params(prec, mlp, rank_tol)
         for i in range(warmup):
             lib.cdwac_solve(sysc, prm)
             log(f"warmup {prec} {i + 1}/{warmup} done")
@@ -393,13 +410,36 @@ def main():
     res["qp_ev"] = [o["qp"] * synth.HARTREE_EV for o in out]
     res["n_evals_mean"] = float(np.mean([o["n_evals"] for o in out]))
 
+    res["inversion_residual"] = lib.cdwac_inversion_residual()[0]
+
+    out64 = None
     if args.fp64_steps > 0 and args.prec != "p64":
-        out64, dt64, st64, _ = run_steps("p64", False, 0, args.fp64_steps)
+        out64, dt64, st64, _ = run_steps("p64", False, args.fp64_warmup, args.fp64_steps)
         err = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(out, out64)]
-        res["fp64_path"] = {"value": s.n_states / dt64, "ms_per_step": dt64 * 1e3, "stages_ms": st64,
+        res["fp64_path"] = {"value": s.n_states / dt64, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
+                            "warmup": args.fp64_warmup, "stages_ms": st64,
                             "n_evals_mean": float(np.mean([o["n_evals"] for o in out64]))}
         res["mev_err_vs_fp64"] = {"max": max(err), "mean": float(np.mean(err)), "per_state": err}
         res["speedup_vs_fp64_path"] = dt64 / dt
+
+    # faster variants of the method, reported beside the stated configuration
+    # and never as its value: the one-product fp16 Pi (W in the fp16 split)
+    # at every node, and the same with Pi, eps^-1 and W only at a skeleton of
+    # the imaginary nodes (W interpolated at the others: an addition to the
+    # method, not in the paper)
+    if args.variant_steps > 0 and args.prec != "p64":
+        variants = {}
+        for name, prec, tol in (("f16_every_node", "f16", 0.0),
+                                ("f16_skeleton_nodes", "f16", cdwac.SKELETON_TOL["f16"])):
+            o_v, dt_v, st_v, l_v = run_steps(prec, use_mlp, 1, args.variant_steps, tol)
+            v = {"value": s.n_states / dt_v, "ms_per_step": dt_v * 1e3, "dtype": DTYPE[prec],
+                 "freq_rank_tol": tol, "imaginary_planes": l_v["planes"][0], "contracted_planes": l_v["planes"][1],
+                 "stages_ms": st_v}
+            if out64 is not None:
+                e = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(o_v, out64)]
+                v["mev_err_vs_fp64"] = {"max": max(e), "mean": float(np.mean(e))}
+            variants[name] = v
+        res["variants"] = variants
 
     if args.calib_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -414,7 +454,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
-        res["cpu_baseline"] = cpu_baseline(s, freq, len(ref_re), s.n_states)
+        res["cpu_baseline"] = cpu_baseline(s, freq, ref_re, s.n_states)
     print(json.dumps(res), flush=True)
 
 

@@ -21,8 +21,9 @@
  *   - Every function returns a cdwac_status.  Arguments are validated before
  *     any kernel is launched; on an error nothing is written to outputs and
  *     cdwac_last_error() describes the problem.  Device-side failures (a
- *     singular pivot in the dielectric inversion) are reported after the
- *     call has synchronised its stream.
+ *     singular pivot in the dielectric inversion, an inverse that fails its
+ *     residual check) are reported after the call has synchronised its
+ *     stream.
  *   - All work is queued on the context's stream; every call returns after
  *     that stream has been synchronised.  One context per host thread.
  *   - Calls that overlap on one context are not allowed.
@@ -46,6 +47,9 @@ typedef enum {
     CDWAC_EHIP = -3,     /* a HIP runtime call failed                                */
     CDWAC_ENOTPD = -4,   /* zero or non-finite pivot while inverting eps = I - Pi    */
     CDWAC_ESTATE = -5,   /* cdwac_qp / cdwac_sigma / cdwac_w_table before prepare    */
+    CDWAC_EFACT = -6,    /* an inverse of eps failed its residual check (element
+                            growth in the unpivoted sweep of the complex-symmetric,
+                            indefinite eps(x + i eta) at a near-real point)          */
     CDWAC_WNOROOT = 1    /* warning: at least one state has no root (qp = NaN)       */
 } cdwac_status;
 
@@ -101,7 +105,8 @@ typedef struct {
     double eta_ref;            /* imaginary part of the near-real references (> 0)         */
     double eta;                /* broadening of the residue term, W(|eps_m - w| + i eta)   */
     double pade_tol;           /* greedy stop: max remaining L1 error <= tol * max|W|      */
-    const double *win_lo;      /* host [n_states]: QP search window                        */
+    const double *win_lo;      /* host [n_states]: QP search window; must contain the
+                                  state's own eps_n, where the root search starts        */
     const double *win_hi;      /* host [n_states]                                          */
     double qp_tol;             /* secant step tolerance (Ha), e.g. 1e-10                   */
     int32_t qp_maxit;          /* secant iterations, e.g. 100                              */
@@ -158,7 +163,11 @@ int cdwac_set_workspace(cdwac_ctx *ctx, void *dev_ptr, size_t bytes);
  * node and near-real reference, Sigma^x, and (d) the greedy Thiele fits of
  * every (n, m) whose residue can enter a window (Sec. 3.4, everything before
  * the QP iteration).  The results stay in the workspace for the calls below;
- * the input arrays may be freed afterwards. */
+ * the input arrays may be freed afterwards.
+ * Every inverse eps^-1 (Eq. bigLambda) is checked on 4 sampled columns eps_j
+ * of eps: CDWAC_EFACT if max|eps^-1 eps_j - e_j| exceeds 1e-8 of
+ * max(|eps^-1| |eps_j|) (cdwac_inversion_residual gives the value).
+ * CDWAC_ENOTPD for a zero or non-finite pivot. */
 int cdwac_prepare(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm);
 
 /* Stage (e): Sigma_n(omega) and the QP root for every state, using the
@@ -187,7 +196,10 @@ int cdwac_solve_batch(cdwac_ctx *ctx, int32_t n_sys, const cdwac_system *sys, co
 
 /* Re Sigma_n(omega) = Sigma^x + Re R_n - I_n (Eq. cdselfe) at n_omega
  * frequencies per state.  omega, sigma: device [n_states][n_omega].
- * Also writes I_n and R_n when i_term / r_term are non-NULL (same shape). */
+ * Also writes I_n and R_n when i_term / r_term are non-NULL (same shape).
+ * Unless the preparation had fit_all = 1, every omega of state j must lie in
+ * its window [win_lo[j], win_hi[j]] widened by 1e-4 Ha: only the orbitals whose
+ * residue can enter that window have Pade models, so CDWAC_EINVAL otherwise. */
 int cdwac_sigma(cdwac_ctx *ctx, int32_t n_omega, const double *omega, double *sigma,
                 double *i_term, double *r_term);
 
@@ -215,6 +227,19 @@ int cdwac_set_g_energies(cdwac_ctx *ctx, const double *eps_g, double eps_fermi);
 int cdwac_evgw(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm, int32_t mode,
                int32_t max_iter, double tol, double *eps_out, int32_t *n_iter, cdwac_state_out *out);
 
+/* G_dH W0 (Sec. 4, the Hedin-shift flavour): a shift dH_n in the denominator
+ * of G, i.e. every energy of G and the Fermi level moved by dH_n in the
+ * self-energy of state n, W and its continuation kept as prepared.  dH_n is
+ * fixed before the QP iteration; the paper gives its place, not its recipe,
+ * and it is taken here as the first-order G0W0 correction at the state's
+ * own energy, dH_n = Re Sigma_n(eps_n) - v^xc_n (prepared G).  Then Eq. (qp_eq)
+ * is solved with Sigma_n of the shifted G (which equals the unshifted
+ * Sigma_n at omega - dH_n).  Needs a preparation with fit_all = 1 (the shifted
+ * residues reach every m).  vxc: host [n_states] or NULL (the value in use);
+ * out: host [n_states]; shift: host [n_states], the dH_n used, or NULL.
+ * Returns CDWAC_WNOROOT if a state has no root. */
+int cdwac_qp_hedin(cdwac_ctx *ctx, const double *vxc, cdwac_state_out *out, double *shift);
+
 /* Sigma_n(omega) by full contour deformation (Sec. 2.3, Eqs. Rn_term,
  * In_term, cdselfe): W^c_nm evaluated directly at every residue
  * |eps_m - omega| + i*eta with f_m(omega) != 0 (Eq. ffact), i.e. one complex
@@ -233,7 +258,8 @@ int cdwac_sigma_cd(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *
  *   A_n(w) = (1/pi) |Im[1 / (w - eps_n - Sigma_n(w) + v^xc_n)]|.
  * omega, spectral: device [n_states][n_omega] (Ha, 1/Ha); sigma_re, sigma_im:
  * device, same shape, or NULL.  vxc: host [n_states] or NULL (the value in
- * use; a non-NULL vxc replaces it, as in cdwac_qp).  n_omega <= 65535 per call. */
+ * use; a non-NULL vxc replaces it, as in cdwac_qp).  n_omega <= 65535 per call.
+ * The window condition of cdwac_sigma applies. */
 int cdwac_spectral(cdwac_ctx *ctx, int32_t n_omega, const double *omega, const double *vxc, double *spectral,
                    double *sigma_re, double *sigma_im);
 
@@ -261,6 +287,13 @@ int cdwac_polarizability(cdwac_ctx *ctx, const cdwac_system *sys, int32_t prec, 
 int cdwac_pade_fit_eval(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const double *u,
                         const double *w, double tol, int32_t n_x, const double *x,
                         double *out, int32_t *n_terms);
+
+/* Largest sampled residual of the inversions of the last preparation,
+ * max|eps^-1 eps_j - e_j| / max(|eps^-1| |eps_j|) over 4 columns j of every
+ * eps(z) (Eq. bigLambda), also after CDWAC_EFACT; matrix: its index (imaginary
+ * planes first, then one per near-real reference), -1 if none was checked.
+ * Host outputs; either may be NULL. */
+int cdwac_inversion_residual(const cdwac_ctx *ctx, double *worst, int32_t *matrix);
 
 /* Per-stage timing with HIP events recorded on the context's stream around
  * the kernels of each stage (0 = off, the default). */
@@ -304,9 +337,11 @@ int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double omega_lo
  * Re Sigma^c(w0), Re Sigma^c(w1), w1 - w0, f(w1), w2 - w1; the network predicts
  * the remaining correction w* - w2, so the seed needs no self-energy
  * evaluation beyond those two.  Inputs are standardised with (mu, sd) and the
- * output is y * out_sd + out_mu.  A seed with |f| <= mlp_accept is the root
- * (flag CDWAC_FLAG_MLP_ACCEPTED); otherwise the secant continues from w1 and
- * the seed, and if that search fails the plain one from w0 and w1 runs. */
+ * output is y * out_sd + out_mu.  A seed with |f| <= mlp_accept and a
+ * physical Z in (0, 1] is the root (flag CDWAC_FLAG_MLP_ACCEPTED); a seed with
+ * |f| <= mlp_accept but Z outside (0, 1] is dropped and the plain search from
+ * w0 and w1 runs; otherwise the secant continues from w1 and the seed, and if
+ * that search fails the plain one from w0 and w1 runs. */
 #define CDWAC_MLP_NIN 8
 #define CDWAC_MLP_NPARAM 4801
 

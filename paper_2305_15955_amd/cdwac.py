@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libcdwac.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cdwac.h")
 
 CDWAC_OK, CDWAC_EINVAL, CDWAC_ENOMEM, CDWAC_EHIP, CDWAC_ENOTPD, CDWAC_ESTATE = 0, -1, -2, -3, -4, -5
+CDWAC_EFACT = -6
 CDWAC_WNOROOT = 1
 CDWAC_P64, CDWAC_B16X3, CDWAC_B16, CDWAC_F16X3, CDWAC_F16 = 0, 1, 2, 3, 4
 FLAG_NOROOT, FLAG_FALLBACK, FLAG_MLP_ACCEPTED = 1, 2, 4
@@ -80,6 +81,7 @@ _SIGNATURES = {
     "cdwac_prepare": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams)]),
     "cdwac_qp": (ctypes.c_int, [_vp, _f64p, ctypes.POINTER(CdwacStateOut)]),
     "cdwac_set_g_energies": (ctypes.c_int, [_vp, _f64p, ctypes.c_double]),
+    "cdwac_qp_hedin": (ctypes.c_int, [_vp, _f64p, ctypes.POINTER(CdwacStateOut), _f64p]),
     "cdwac_evgw": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams), ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_double, _f64p, _i32p, ctypes.POINTER(CdwacStateOut)]),
     "cdwac_sigma_cd": (ctypes.c_int, [_vp, ctypes.POINTER(CdwacSystem), ctypes.POINTER(CdwacParams),
@@ -104,6 +106,7 @@ _SIGNATURES = {
     "cdwac_spectral": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _f64p, _vp, _vp, _vp]),
     "cdwac_plane_counts": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "cdwac_get_timing_segments": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "cdwac_inversion_residual": (ctypes.c_int, [_vp, _f64p, ctypes.POINTER(ctypes.c_int32)]),
     "cdwac_mlp_set_model": (ctypes.c_int, [_vp, _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_float]),
     "cdwac_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "cdwac_mlp_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp]),
@@ -292,6 +295,16 @@ class Cdwac:
         _check(self.ctx, rc, allow_warn=True)
         return _outs(out)
 
+    def cdwac_qp_hedin(self, n_states: int, vxc=None):
+        """G_dH W0 roots -> (state results, the shifts dH_n used)."""
+        out = (CdwacStateOut * n_states)()
+        vx = None if vxc is None else np.ascontiguousarray(vxc, np.float64)
+        dh = np.zeros(n_states, np.float64)
+        rc = self.lib.cdwac_qp_hedin(self.ctx, None if vx is None else _np_ptr(vx, ctypes.c_double), out,
+                                     _np_ptr(dh, ctypes.c_double))
+        _check(self.ctx, rc, allow_warn=True)
+        return _outs(out), dh
+
     def cdwac_solve(self, sysc, prm):
         out = (CdwacStateOut * sysc.n_states)()
         rc = self.lib.cdwac_solve(self.ctx, ctypes.byref(sysc), ctypes.byref(prm), out)
@@ -437,6 +450,12 @@ class Cdwac:
         n = np.zeros(len(self.STAGES), np.int32)
         _check(self.ctx, self.lib.cdwac_get_timing_segments(self.ctx, _np_ptr(n, ctypes.c_int32), len(n)))
         return dict(zip(self.STAGES, n.tolist()))
+
+    def cdwac_inversion_residual(self):
+        """(largest sampled residual ratio of the last preparation's inversions, its matrix index)."""
+        r, m = ctypes.c_double(0.0), ctypes.c_int32(-1)
+        _check(self.ctx, self.lib.cdwac_inversion_residual(self.ctx, ctypes.byref(r), ctypes.byref(m)))
+        return r.value, m.value
 
     # -- learned seed -------------------------------------------------------
     def cdwac_mlp_set_model(self, theta, mu, sd, out_mu: float, out_sd: float):

@@ -28,6 +28,13 @@ constexpr size_t kPiListPad = 8 * 128;
 // every self-energy evaluation of the solver finds a Pade model.
 constexpr double kFitMargin = 1e-4;
 
+// Largest accepted sampled residual of an inversion, max|eps^-1 eps_j - e_j|
+// relative to max(|eps^-1| |eps_j|): a backward-stable inverse stays within a
+// small multiple of the unit roundoff (about 1e-15 measured); element growth
+// in the unpivoted sweep of an indefinite eps(x + i eta) raises it by the
+// growth factor.  Above this the inverse has lost more than half its digits.
+constexpr double kFactTol = 1e-8;
+
 struct Region {
     size_t off = 0, bytes = 0;
 };
@@ -41,12 +48,12 @@ struct Plan {
     int64_t K, kpad;
     // persistent regions
     Region eps, eps_g, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
-        fit_m, w_im, w_re, coef, node, nterm, qpout, err;
+        fit_m, w_im, w_re, coef, node, nterm, qpout, err, hedin;
     // transient regions (prepare only)
     Region zr, zi, part, idflag, amax, sf, cw, cw64, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c,
         dscr_r, lh, ll,
         bt64, bh, bl, bf64, bfh, bfl, partial_im, partial_re, rowsel, ref_u, ref_w, x32, yh, yl, t_pi, t_w,
-        t_wf, pmap, imnode, imrest, tmat, rowsum;
+        t_wf, pmap, imnode, imrest, tmat, rowsum, fcols, fcolidx, fres;
     size_t total = 0;
 };
 
@@ -113,6 +120,9 @@ struct cdwac_ctx {
     size_t pool_used = 0;
     double stage_ms[CDWAC_N_STAGES] = {};
     int32_t stage_n[CDWAC_N_STAGES] = {};
+    // sampled residual of the inversions of the last preparation
+    double fact_ratio = 0.0;
+    int32_t fact_mat = -1;
 };
 
 namespace {
@@ -194,9 +204,15 @@ int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p
     if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return fail(ctx, CDWAC_EINVAL, "eta must be >= 0");
     if (!(p->pade_tol >= 0.0)) return fail(ctx, CDWAC_EINVAL, "pade_tol must be >= 0");
     if (!p->win_lo || !p->win_hi) return fail(ctx, CDWAC_EINVAL, "NULL QP window");
-    for (int j = 0; j < s->n_states; ++j)
+    for (int j = 0; j < s->n_states; ++j) {
         if (!std::isfinite(p->win_lo[j]) || !std::isfinite(p->win_hi[j]) || !(p->win_lo[j] < p->win_hi[j]))
             return fail(ctx, CDWAC_EINVAL, "QP window %d must satisfy lo < hi", j);
+        // the root search starts at eps_n (Eq. qp_eq)
+        const double e_n = s->eps[s->state_idx[j]];
+        if (!(p->win_lo[j] <= e_n && e_n <= p->win_hi[j]))
+            return fail(ctx, CDWAC_EINVAL, "QP window %d [%g, %g] does not contain its state's energy %g", j,
+                        p->win_lo[j], p->win_hi[j], e_n);
+    }
     if (!(p->qp_tol > 0.0) || p->qp_maxit < 1) return fail(ctx, CDWAC_EINVAL, "qp_tol > 0 and qp_maxit >= 1 required");
     if (p->prec < CDWAC_P64 || p->prec > CDWAC_F16) return fail(ctx, CDWAC_EINVAL, "unknown precision %d", p->prec);
     if (p->use_mlp_seed != 0 && p->use_mlp_seed != 1) return fail(ctx, CDWAC_EINVAL, "use_mlp_seed must be 0 or 1");
@@ -422,6 +438,8 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     add(P, P.node, sizeof(double) * 2 * (size_t)std::max(P.n_fit, 1) * P.n_pts);
     add(P, P.nterm, sizeof(int) * std::max(P.n_fit, 1));
     add(P, P.qpout, sizeof(QpOut) * P.S);
+    // G_dH W0: evaluation points eps_n, Sigma_n(eps_n), shifts dH_n
+    add(P, P.hedin, sizeof(double) * 3 * (size_t)P.S);
     add(P, P.err, sizeof(int) * 4);
     // transient
     add(P, P.zr, sizeof(double) * P.n_f);
@@ -433,6 +451,10 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     add(P, P.imrest, sizeof(int) * P.n_freq);
     add(P, P.tmat, sizeof(double) * (size_t)P.n_freq * P.n_freq);
     add(P, P.rowsum, sizeof(double) * P.npad);
+    // residual check of the inversions: sampled columns of every plane of eps
+    add(P, P.fcols, sizeof(double) * (size_t)P.n_f * kFactCols * P.npad);
+    add(P, P.fcolidx, sizeof(int) * kFactCols);
+    add(P, P.fres, sizeof(unsigned long long) * 2 * (size_t)(P.n_imp + P.n_re) * kFactCols);
     // operand maxima: [0] |O^ia|, [1] |O^nm|, [2..2+F) |c_f|, [2+F..2+2F) |Lambda_f|
     add(P, P.amax, sizeof(uint32_t) * (2 + 2 * (size_t)P.n_f));
     // scales: [0] x, [1] B, cfac[F], pi_unscale[F], lam_scale[F], w_unscale[F]
@@ -867,6 +889,15 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     }
     // (a2) eps^-1 by blocked sweeps, Lambda = eps^-1 - I
     TRY(seg_begin(ctx, 2));
+    {
+        // columns of eps kept for the residual check of the inverses
+        int cols[kFactCols];
+        for (int c = 0; c < kFactCols; ++c) cols[c] = (int)((int64_t)c * (P.n_aux - 1) / (kFactCols - 1));
+        TRY(upload(ctx, at<int>(ctx, P.fcolidx), cols, kFactCols));
+        HIPCK(hipMemsetAsync(at<unsigned long long>(ctx, P.fres), 0, P.fres.bytes, st));
+        launch_fact_gather(st, at<double>(ctx, P.E), P.npad, P.n_f, at<int>(ctx, P.fcolidx), at<double>(ctx, P.fcols));
+        LAUNCHCK();
+    }
     if (P.n_re > 0) {
         // the complex planes on the second stream, with 64-wide pivots (eps is
         // complex symmetric and indefinite there and no pivoting is done, so
@@ -894,6 +925,9 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     TRY(seg_begin(ctx, 3));
     launch_finalize_lambda(st, at<double>(ctx, P.E), P.npad, P.n_f, at<int>(ctx, P.idflag),
                            f64 ? nullptr : amax + 2 + P.n_f);
+    LAUNCHCK();
+    launch_fact_residual(st, at<double>(ctx, P.E), P.npad, P.n_imp, P.n_re, P.n_imp, at<int>(ctx, P.fcolidx),
+                         at<double>(ctx, P.fcols), at<unsigned long long>(ctx, P.fres));
     LAUNCHCK();
     if (!f64) {
         launch_scales_w(st, amax + 2 + P.n_f, P.n_f, sf, lam_scale, w_unscale);
@@ -962,6 +996,8 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     TRY(seg_end(ctx));
     int herr[4] = {0, 0, 0, 0};
     HIPCK(hipMemcpyAsync(herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
+    std::vector<unsigned long long> fres(P.fres.bytes / sizeof(unsigned long long));
+    HIPCK(hipMemcpyAsync(fres.data(), at<unsigned long long>(ctx, P.fres), P.fres.bytes, hipMemcpyDeviceToHost, st));
     std::vector<double> rows(use_id ? P.npad : 0);
     if (use_id) HIPCK(hipMemcpyAsync(rows.data(), at<double>(ctx, P.rowsum), sizeof(double) * P.npad,
                                      hipMemcpyDeviceToHost, st));
@@ -978,6 +1014,26 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
         if (!(om_bound <= hs.omega_hi)) return prepare_impl(ctx, sys, prm, false, sink);
     }
     if (herr[0] & 1) return fail(ctx, CDWAC_ENOTPD, "zero or non-finite pivot while inverting eps = I - Pi");
+    // sampled residual of every inversion (a NaN counts as a failure)
+    ctx->fact_ratio = 0.0;
+    ctx->fact_mat = -1;
+    for (int m = 0; m < P.n_imp + P.n_re; ++m)
+        for (int c = 0; c < kFactCols; ++c) {
+            double r, b;
+            std::memcpy(&r, &fres[2 * ((size_t)m * kFactCols + c)], sizeof r);
+            std::memcpy(&b, &fres[2 * ((size_t)m * kFactCols + c) + 1], sizeof b);
+            const double q = r == 0.0 ? 0.0 : r / b;
+            if (!(q <= ctx->fact_ratio)) {
+                ctx->fact_ratio = std::isnan(q) ? INFINITY : q;
+                ctx->fact_mat = m;
+            }
+        }
+    if (!(ctx->fact_ratio <= kFactTol))
+        return fail(ctx, CDWAC_EFACT,
+                    "inverse of eps failed its residual check: max|eps^-1 eps_j - e_j| = %.3g of |eps^-1||eps_j| "
+                    "(matrix %d; %s), above %.0e", ctx->fact_ratio, ctx->fact_mat,
+                    ctx->fact_mat >= P.n_imp ? "near-real reference, complex symmetric" : "imaginary node",
+                    kFactTol);
     ctx->hs = hs;
     ctx->prepared = true;
     return CDWAC_OK;
@@ -1005,6 +1061,42 @@ int cdwac_qp(cdwac_ctx* ctx, const double* vxc, cdwac_state_out* out) {
     HIPCK(hipMemcpyAsync(out, at<QpOut>(ctx, P.qpout), sizeof(QpOut) * P.S, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     TRY(seg_collect(ctx));
+    for (int j = 0; j < P.S; ++j)
+        if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
+    return CDWAC_OK;
+}
+
+int cdwac_qp_hedin(cdwac_ctx* ctx, const double* vxc, cdwac_state_out* out, double* shift) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (!ctx->prepared) return fail(ctx, CDWAC_ESTATE, "cdwac_qp_hedin called before cdwac_prepare");
+    if (!out) return fail(ctx, CDWAC_EINVAL, "out is NULL");
+    if (!ctx->hs.fit_all)
+        return fail(ctx, CDWAC_EINVAL, "the shifted G needs a preparation with fit_all = 1 (a model for every m)");
+    const Plan& P = ctx->plan;
+    if (vxc && !finite_all(vxc, P.S)) return fail(ctx, CDWAC_EINVAL, "non-finite vxc");
+    if (ctx->hs.use_mlp && !ctx->have_mlp) return fail(ctx, CDWAC_EINVAL, "no MLP model installed");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (vxc) TRY(upload(ctx, at<double>(ctx, P.vxc), vxc, P.S));
+    // dH_n = Re Sigma_n(eps_n) - v^xc_n with the unshifted G, before the QP iteration
+    double* hv = at<double>(ctx, P.hedin);
+    std::vector<double> e_n(P.S), sig(P.S), vx(P.S), dh(P.S);
+    for (int j = 0; j < P.S; ++j) e_n[j] = ctx->hs.eps[ctx->hs.state_idx[j]];
+    TRY(upload(ctx, hv, e_n.data(), P.S));
+    QpArgs a = qp_args(ctx);
+    launch_sigma(st, a, 1, hv, hv + P.S, nullptr, nullptr);
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(sig.data(), hv + P.S, sizeof(double) * P.S, hipMemcpyDeviceToHost, st));
+    HIPCK(hipMemcpyAsync(vx.data(), at<double>(ctx, P.vxc), sizeof(double) * P.S, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    for (int j = 0; j < P.S; ++j) dh[j] = sig[j] - vx[j];
+    TRY(upload(ctx, hv + 2 * P.S, dh.data(), P.S));
+    a.g_shift = hv + 2 * P.S;
+    launch_qp(st, a, at<QpOut>(ctx, P.qpout));
+    LAUNCHCK();
+    HIPCK(hipMemcpyAsync(out, at<QpOut>(ctx, P.qpout), sizeof(QpOut) * P.S, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (shift) std::copy(dh.begin(), dh.end(), shift);
     for (int j = 0; j < P.S; ++j)
         if (out[j].flags & CDWAC_FLAG_NOROOT) return CDWAC_WNOROOT;
     return CDWAC_OK;
@@ -1329,6 +1421,30 @@ int cdwac_sigma_cd(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* 
     return CDWAC_OK;
 }
 
+namespace {
+// Without fit_all only the orbitals whose residue can enter a state's window
+// have Pade models (Eq. ffact): an omega outside the window (widened by the
+// Z-factor step) would silently drop residues, so it is rejected.
+int check_omega_in_fit_range(cdwac_ctx* ctx, int32_t n_omega, const double* omega) {
+    if (ctx->hs.fit_all || n_omega == 0) return CDWAC_OK;
+    const int S = ctx->plan.S;
+    std::vector<double> om((size_t)S * n_omega);
+    HIPCK(hipMemcpyAsync(om.data(), omega, sizeof(double) * om.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    for (int j = 0; j < S; ++j) {
+        const double lo = ctx->hs.win_lo[j] - kFitMargin, hi = ctx->hs.win_hi[j] + kFitMargin;
+        for (int k = 0; k < n_omega; ++k) {
+            const double w = om[(size_t)j * n_omega + k];
+            if (!(lo <= w && w <= hi))
+                return fail(ctx, CDWAC_EINVAL,
+                            "omega[%d][%d] = %g lies outside the fitted window [%g, %g] of its state (prepare "
+                            "with fit_all = 1 to evaluate anywhere)", j, k, w, lo, hi);
+        }
+    }
+    return CDWAC_OK;
+}
+}  // namespace
+
 int cdwac_sigma(cdwac_ctx* ctx, int32_t n_omega, const double* omega, double* sigma, double* i_term,
                 double* r_term) {
     if (!ctx) return CDWAC_EINVAL;
@@ -1336,6 +1452,7 @@ int cdwac_sigma(cdwac_ctx* ctx, int32_t n_omega, const double* omega, double* si
     if (n_omega < 0 || (n_omega > 0 && (!omega || !sigma))) return fail(ctx, CDWAC_EINVAL, "bad omega/sigma");
     if (n_omega > 65535) return fail(ctx, CDWAC_EINVAL, "n_omega must be <= 65535");
     HIPCK(hipSetDevice(ctx->device));
+    TRY(check_omega_in_fit_range(ctx, n_omega, omega));
     QpArgs a = qp_args(ctx);
     launch_sigma(ctx->stream, a, n_omega, omega, sigma, i_term, r_term);
     LAUNCHCK();
@@ -1353,6 +1470,7 @@ int cdwac_spectral(cdwac_ctx* ctx, int32_t n_omega, const double* omega, const d
         for (int j = 0; j < ctx->plan.S; ++j)
             if (!std::isfinite(vxc[j])) return fail(ctx, CDWAC_EINVAL, "vxc[%d] is not finite", j);
     HIPCK(hipSetDevice(ctx->device));
+    TRY(check_omega_in_fit_range(ctx, n_omega, omega));
     if (vxc) TRY(upload(ctx, at<double>(ctx, ctx->plan.vxc), vxc, ctx->plan.S));
     QpArgs a = qp_args(ctx);
     launch_spectral(ctx->stream, a, n_omega, omega, spectral, sigma_re, sigma_im);
@@ -1568,6 +1686,13 @@ int cdwac_plane_counts(const cdwac_ctx* ctx, int32_t* n_imag, int32_t* n_planes)
     if (!ctx->prepared) return CDWAC_ESTATE;
     *n_imag = ctx->plan.n_imp;
     *n_planes = ctx->plan.n_f;
+    return CDWAC_OK;
+}
+
+int cdwac_inversion_residual(const cdwac_ctx* ctx, double* worst, int32_t* matrix) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (worst) *worst = ctx->fact_ratio;
+    if (matrix) *matrix = ctx->fact_mat;
     return CDWAC_OK;
 }
 

@@ -196,22 +196,24 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
 // operand panels in its L2; the W contraction's from 4 x 8 blocks.
 // ============================================================================
 
-constexpr int GT = 256, GK = 32, KGR = GK / 8;
+constexpr int GT = 256;
 constexpr int kGemmThreads = 512;
-// uint4 slots of the LDS ring (128 KiB: 2 stages of 64 KiB with the split,
-// 4 stages of 32 KiB without it), of one operand per stage, of a stage, and
+// K chunk GKX (a multiple of 16), k-groups of 8 per chunk, uint4 slots of the
+// LDS ring (SLOTSX: 8192 = 128 KiB), of one operand per stage, of a stage, and
 // the ring depth
-template <bool SPLIT>
+template <bool SPLIT, int GKX = 32, int SLOTSX = 8192>
 struct Ring {
-    static constexpr int SLOTS = 8192;
-    static constexpr int OP = (SPLIT ? 2 : 1) * KGR * GT;
+    static constexpr int GK = GKX;
+    static constexpr int KG = GKX / 8;
+    static constexpr int PL = SPLIT ? 2 : 1;
+    static constexpr int SLOTS = SLOTSX;
+    static constexpr int OP = PL * KG * GT;
     static constexpr int STAGE = 2 * OP;
     static constexpr int NST = SLOTS / STAGE;
+    // 64-row-block loads per chunk and wave: 2 operands x PL planes x KG
+    // k-groups x 4 row blocks over 8 waves
+    static constexpr int LPW = 2 * PL * KG * 4 / 8;
 };
-// 64-row-block loads per chunk: 2 operands x 2 planes x KGR k-groups x 4 row
-// blocks with the hi/lo split, the hi planes alone without it
-template <bool SPLIT>
-constexpr int loads_per_wave() { return (SPLIT ? 2 : 1) * 2 * KGR * 4 / 8; }
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -223,46 +225,44 @@ constexpr int wait_vm_lgkm0(int n) { return ((n >> 4) << 14) | (7 << 4) | (n & 1
 // flight for the next chunk.  Callers wait for what must be complete first.
 __device__ inline void stage_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// Issues this wave's share (8 of 64 row-block loads, 4 of 32 without the
-// split) of chunk k0 into stage st.
-template <bool SPLIT>
+// Issues this wave's share of the row-block loads of chunk k0 into stage st.
+template <bool SPLIT, class RG>
 __device__ inline void gemm_issue(uint4* lds, int st, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
                                   const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl, int64_t K,
                                   int64_t k0, int w, int lane) {
-    constexpr int per = loads_per_wave<SPLIT>();
+    constexpr int per = RG::LPW, per_op = RG::PL * RG::KG * 4;
 #pragma unroll
     for (int q = 0; q < per; ++q) {
         const int u = w * per + q;
-        const int op = SPLIT ? u >> 5 : u >> 4;       // operand A or B
-        const int v = SPLIT ? u & 31 : u & 15;
-        const int pl = SPLIT ? v >> 4 : 0, kg = (v >> 2) & 3, rb = v & 3;
+        const int op = u / per_op;                    // operand A or B
+        const int v = u % per_op;
+        const int pl = v / (RG::KG * 4), kg = (v >> 2) % RG::KG, rb = v & 3;
         const uint16_t* base = op ? (pl ? bl : bh) : (pl ? al : ah);
         const uint16_t* g = base + (int64_t)rb * 64 * K + (k0 + kg * 8) * 64 + lane * 8;
-        const int slot = op * Ring<SPLIT>::OP + (pl * KGR + kg) * GT + rb * 64;
-        __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(lds + st * Ring<SPLIT>::STAGE + slot), 16, 0,
-                                         0);
+        const int slot = op * RG::OP + (pl * RG::KG + kg) * GT + rb * 64;
+        __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)(lds + st * RG::STAGE + slot), 16, 0, 0);
     }
 }
 
-template <int ET, bool SPLIT>
+template <int ET, bool SPLIT, class RG>
 __device__ inline void gemm_chunk(const uint4* lds, int st, int r0, int c0, int lane, v16f (&acc)[2][4]) {
     typedef typename Elem<ET>::vec V;
-    const uint4* sa = lds + st * Ring<SPLIT>::STAGE;
-    const uint4* sb = sa + Ring<SPLIT>::OP;
+    const uint4* sa = lds + st * RG::STAGE;
+    const uint4* sb = sa + RG::OP;
     const int r = lane & 31, hg = lane >> 5;
 #pragma unroll
-    for (int ks = 0; ks < GK / 16; ++ks) {
+    for (int ks = 0; ks < RG::GK / 16; ++ks) {
         const int kg = ks * 2 + hg;
         V ahv[2], alv[2], bhv[4], blv[4];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             ahv[b] = __builtin_bit_cast(V, sa[kg * GT + r0 + b * 32 + r]);
-            if (SPLIT) alv[b] = __builtin_bit_cast(V, sa[(KGR + kg) * GT + r0 + b * 32 + r]);
+            if (SPLIT) alv[b] = __builtin_bit_cast(V, sa[(RG::KG + kg) * GT + r0 + b * 32 + r]);
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             bhv[b] = __builtin_bit_cast(V, sb[kg * GT + c0 + b * 32 + r]);
-            if (SPLIT) blv[b] = __builtin_bit_cast(V, sb[(KGR + kg) * GT + c0 + b * 32 + r]);
+            if (SPLIT) blv[b] = __builtin_bit_cast(V, sb[(RG::KG + kg) * GT + c0 + b * 32 + r]);
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -277,33 +277,35 @@ __device__ inline void gemm_chunk(const uint4* lds, int st, int r0, int c0, int 
     }
 }
 
-// acc = A[rows 0..256) * B[rows 0..256)^T over K (multiple of GK); A and B
-// point at the first row block of the tile.  Wave w owns rows
+// acc = A[rows 0..256) * B[rows 0..256)^T over K (multiple of RG::GK); A and
+// B point at the first row block of the tile.  Wave w owns rows
 // 64 (w / 2) .. +64 and columns 128 (w % 2) .. +128.
-template <int ET, bool SPLIT>
+template <int ET, bool SPLIT, class RG>
 __device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
                                  const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl, int64_t K,
                                  v16f (&acc)[2][4]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int r0 = (w >> 1) * 64, c0 = (w & 1) * 128;
-    const int64_t nk = K / GK;
+    const int64_t nk = K / RG::GK;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = v16f{};
-    constexpr int NST = Ring<SPLIT>::NST;
-    constexpr int ahead = (NST - 2) * loads_per_wave<SPLIT>();   // loads of later chunks left in flight
+    constexpr int NST = RG::NST;
+    constexpr int ahead = (NST - 2) * RG::LPW;   // loads of later chunks left in flight
+    static_assert(ahead < 64, "vmcnt holds at most 63 outstanding loads");
 #pragma unroll
     for (int j = 0; j < NST - 1; ++j)
-        if (j < nk) gemm_issue<SPLIT>(lds, j, ah, al, bh, bl, K, j * GK, w, lane);
+        if (j < nk) gemm_issue<SPLIT, RG>(lds, j, ah, al, bh, bl, K, j * RG::GK, w, lane);
     for (int64_t i = 0; i < nk; ++i) {
         // chunk i has landed (own loads) and every wave is done with chunk i-1
         if (i + NST - 2 < nk) __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(ahead));
         else __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
         stage_barrier();
         if (i + NST - 1 < nk)
-            gemm_issue<SPLIT>(lds, (int)((i + NST - 1) % NST), ah, al, bh, bl, K, (i + NST - 1) * GK, w, lane);
-        gemm_chunk<ET, SPLIT>(lds, (int)(i % NST), r0, c0, lane, acc);
+            gemm_issue<SPLIT, RG>(lds, (int)((i + NST - 1) % NST), ah, al, bh, bl, K, (i + NST - 1) * RG::GK, w,
+                                  lane);
+        gemm_chunk<ET, SPLIT, RG>(lds, (int)(i % NST), r0, c0, lane, acc);
     }
 }
 
@@ -317,6 +319,11 @@ __device__ inline int out_col(int w, int bj, int lane) { return (w & 1) * 128 + 
 // eps_f = delta_f I - Pi_f for the tiles of a work list (pi_worklist): entry
 // {fb << 16 | I, J} is tile (I, J) of plane f = fmap[fb] (B = prescaled Y_f,
 // batch slot fb); {-1, -1} is an empty slot.
+// Ring of the polarizability contraction: 32-wide K chunks in 2 stages of
+// 64 KiB with the split, 4 stages of 32 KiB without it.
+template <bool SPLIT>
+using PiRing = Ring<SPLIT, 32, 8192>;
+
 template <int ET, bool SPLIT>
 __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __restrict__ xh,
                                                           const uint16_t* __restrict__ xl,
@@ -327,7 +334,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
                                                           const double* __restrict__ pi_unscale,
                                                           const int* __restrict__ idflag, double* __restrict__ E,
                                                           int npad) {
-    __shared__ uint4 lds[Ring<SPLIT>::SLOTS];
+    __shared__ uint4 lds[PiRing<SPLIT>::SLOTS];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int2 e = work[bid];
     if (e.x < 0) return;
@@ -335,7 +342,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
     const int64_t ao = (int64_t)I * GT * kpad;
     const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GT * kpad;
     v16f acc[2][4];
-    gemm_tile<ET, SPLIT>(lds, xh + ao, xl + ao, yh + bo, yl + bo, kpad, acc);
+    gemm_tile<ET, SPLIT, PiRing<SPLIT>>(lds, xh + ao, xl + ao, yh + bo, yl + bo, kpad, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double id = idflag[f] ? 1.0 : 0.0;
     const double us = pi_unscale[f];
@@ -352,6 +359,10 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
             }
 }
 
+// Ring of the W contraction (same as the polarizability's).
+template <bool SPLIT>
+using WRing = Ring<SPLIT, 32, 8192>;
+
 // partial[fl][I][c] = sum_{P in row block I} B[c][P] (Lambda_f B^T)[P][c]
 template <int ET, bool SPLIT>
 __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restrict__ lh,
@@ -362,7 +373,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
                                                          const int2* __restrict__ tiles, int n_tiles, int f0,
                                                          const double* __restrict__ w_unscale,
                                                          double* __restrict__ partial) {
-    __shared__ uint4 lds[Ring<SPLIT>::SLOTS];
+    __shared__ uint4 lds[WRing<SPLIT>::SLOTS];
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fl = bid / n_tiles;
     const int2 tile = tiles[bid % n_tiles];
@@ -371,7 +382,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
     const int64_t lo = (int64_t)(f0 + fl) * npad * npad + (int64_t)I * GT * npad;
     const int64_t bo = (int64_t)J * GT * npad;
     v16f acc[2][4];
-    gemm_tile<ET, SPLIT>(lds, lh + lo, ll + lo, bh + bo, bl + bo, npad, acc);
+    gemm_tile<ET, SPLIT, WRing<SPLIT>>(lds, lh + lo, ll + lo, bh + bo, bl + bo, npad, acc);
     // the column sums reuse the ring once every wave is done reading it
     __syncthreads();
     double (*red)[GT] = reinterpret_cast<double (*)[GT]>(lds);

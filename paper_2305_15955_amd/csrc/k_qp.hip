@@ -60,9 +60,12 @@ __device__ inline double integral_partial(const QpArgs& A, int s, double omega, 
     return isum;
 }
 
-// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).
-__device__ void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R,
+// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).  A
+// shift dH of every energy of G and of the Fermi level (G_dH W0) enters only
+// through omega - eps_m and eps_F - eps_m, so it is applied as omega - dH.
+__device__ void sigma_terms(const QpArgs& A, int s, double omega_in, Shared& sh, double& I, double& R,
                             double* Ri = nullptr) {
+    const double omega = A.g_shift ? omega_in - A.g_shift[s] : omega_in;
     const double isum = integral_partial(A, s, omega, sh);
     double rsum = 0.0, risum = 0.0;
     const int m0 = A.m0[s], m1 = A.m1[s], foff = A.fit_off[s];
@@ -193,10 +196,15 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
         if (seed >= lo && seed <= hi) {
             const double fs = f(seed);
             if (fabs(fs) <= A.mlp_accept) {
-                root = seed;
-                zf = z_factor(seed);
-                flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
-                done = true;
+                // the same physical-Z test as a secant root: a seed on an
+                // unphysical crossing falls through to the plain search
+                const double z = z_factor(seed);
+                if (0.0 < z && z <= 1.0) {
+                    root = seed;
+                    zf = z;
+                    flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
+                    done = true;
+                }
             } else {
                 // the secant continues from omega_1 and the seed
                 done = secant(w1, f1, seed, fs);

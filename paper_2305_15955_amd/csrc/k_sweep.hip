@@ -529,4 +529,92 @@ void launch_sweep2(hipStream_t s, double* E, int npad, int n_real, int n_cplx, i
     launch_sweep2_t<true>(s, E, npad, n_cplx, cbase, dscr_c, dinv_c, pbuf_c, qbuf_c, err);
 }
 
+// ---------------------------------------------------------------------------
+// Residual check of the computed inverses.  Before the sweep, kFactCols
+// columns eps_j of every plane are copied out of the lower-triangle storage;
+// after Lambda = eps^-1 - I has been formed (Re plane: Re eps^-1 - I; Im
+// plane: Im eps^-1), r = (Lambda + I) eps_j - e_j = eps^-1 eps_j - e_j is
+// formed in FP64 together with the scale b = |eps^-1| |eps_j| (elementwise
+// moduli).  A backward-stable inverse keeps max|r| / max b at a small multiple
+// of the unit roundoff; element growth in the unpivoted sweep of an indefinite
+// complex-symmetric eps(x + i eta) raises it by the growth factor.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fact_gather(const double* __restrict__ E, int npad,
+                                                     const int* __restrict__ cols,
+                                                     double* __restrict__ out) {
+    const int f = blockIdx.x, c = blockIdx.y;
+    const int j = cols[c];
+    const double* Ef = E + (int64_t)f * npad * npad;
+    double* o = out + ((int64_t)f * kFactCols + c) * npad;
+    for (int i = threadIdx.x; i < npad; i += 256)
+        o[i] = i >= j ? Ef[(int64_t)i * npad + j] : Ef[(int64_t)j * npad + i];
+}
+
+__device__ inline double wave_sum_d(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One wave per row i of one matrix (4 rows per workgroup); res[mat][c] holds
+// {max_i |r_i|, max_i b_i} as the bit patterns of non-negative doubles, which
+// order like the values (atomicMax on 64-bit integers).
+template <bool C>
+__global__ __launch_bounds__(256) void k_fact_residual(const double* __restrict__ E, int npad, int cbase,
+                                                       const int* __restrict__ cols,
+                                                       const double* __restrict__ saved,
+                                                       unsigned long long* __restrict__ res, int res_base) {
+    const int mat = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= npad) return;
+    const int64_t n2 = (int64_t)npad * npad;
+    const int pr = C ? cbase + 2 * mat : cbase + mat;
+    const double* Lr = E + (int64_t)pr * n2 + (int64_t)i * npad;
+    const double* Li = Lr + n2;
+    const double* sr = saved + (int64_t)pr * kFactCols * npad;
+    const double* si = sr + (int64_t)kFactCols * npad;
+    double ar[kFactCols], ai[kFactCols], b[kFactCols];
+#pragma unroll
+    for (int c = 0; c < kFactCols; ++c) ar[c] = ai[c] = b[c] = 0.0;
+    for (int k = lane; k < npad; k += 64) {
+        const double lr = Lr[k] + (k == i ? 1.0 : 0.0);
+        const double li = C ? Li[k] : 0.0;
+        const double lm = C ? sqrt(lr * lr + li * li) : fabs(lr);
+#pragma unroll
+        for (int c = 0; c < kFactCols; ++c) {
+            const double er = sr[(int64_t)c * npad + k];
+            const double ei = C ? si[(int64_t)c * npad + k] : 0.0;
+            ar[c] += lr * er - li * ei;
+            ai[c] += lr * ei + li * er;
+            b[c] += lm * (C ? sqrt(er * er + ei * ei) : fabs(er));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kFactCols; ++c) {
+        const double rr = wave_sum_d(ar[c]) - (i == cols[c] ? 1.0 : 0.0);
+        const double ri = wave_sum_d(ai[c]);
+        const double bb = wave_sum_d(b[c]);
+        if (lane == 0) {
+            unsigned long long* o = res + 2 * ((int64_t)(res_base + mat) * kFactCols + c);
+            atomicMax(o, (unsigned long long)__double_as_longlong(sqrt(rr * rr + ri * ri)));
+            atomicMax(o + 1, (unsigned long long)__double_as_longlong(bb));
+        }
+    }
+}
+
+void launch_fact_gather(hipStream_t s, const double* E, int npad, int n_f, const int* cols, double* out) {
+    if (n_f > 0) hipLaunchKernelGGL(k_fact_gather, dim3(n_f, kFactCols), dim3(256), 0, s, E, npad, cols, out);
+}
+
+void launch_fact_residual(hipStream_t s, const double* E, int npad, int n_real, int n_cplx, int cbase,
+                          const int* cols, const double* saved, unsigned long long* res) {
+    const unsigned gx = (unsigned)((npad + 3) / 4);
+    if (n_real > 0)
+        hipLaunchKernelGGL(k_fact_residual<false>, dim3(gx, n_real), dim3(256), 0, s, E, npad, 0, cols, saved, res,
+                           0);
+    if (n_cplx > 0)
+        hipLaunchKernelGGL(k_fact_residual<true>, dim3(gx, n_cplx), dim3(256), 0, s, E, npad, cbase, cols, saved,
+                           res, n_real);
+}
+
 }  // namespace cdwac

@@ -31,6 +31,7 @@ struct QpArgs {
     const double* vxc;       // [S]
     const double* win_lo;    // [S]
     const double* win_hi;    // [S]
+    const double* g_shift;   // [S] shift of G's energies per state (G_dH W0), or nullptr
     double eta, eps_f, qp_tol;
     int qp_maxit;
     int use_mlp;
@@ -103,6 +104,13 @@ void launch_sweep(hipStream_t s, double* E, int npad, int n_real, int n_cplx, in
 void launch_sweep2(hipStream_t s, double* E, int npad, int n_real, int n_cplx, int cbase, double* dscr_r,
                    double* dscr_c, double* dinv_r, double* pbuf_r, double* qbuf_r, double* dinv_c, double* pbuf_c,
                    double* qbuf_c, int* err);
+// residual check of the inverses: kFactCols sampled columns of every plane of
+// eps (before the sweep), then {max|eps^-1 eps_j - e_j|, max |eps^-1||eps_j|}
+// per matrix and column into res [n_real + n_cplx][kFactCols][2]
+constexpr int kFactCols = 4;
+void launch_fact_gather(hipStream_t s, const double* E, int npad, int n_f, const int* cols, double* out);
+void launch_fact_residual(hipStream_t s, const double* E, int npad, int n_real, int n_cplx, int cbase,
+                          const int* cols, const double* saved, unsigned long long* res);
 
 // k_thiele.hip
 void launch_thiele_fit(hipStream_t s, int n_fit, int n_pts, const double* u, const double* w, double tol,

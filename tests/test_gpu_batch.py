@@ -5,21 +5,20 @@ launch and the QP roots of all states in one launch.
 * A small FP64 batch: every QP energy equals the one-system path bit for bit
   (same kernels on the same data) and the oracle to 1e-9 relative.
 * The 48-system batch (N_mo uniform in [100, 1200], N_aux = 3.3 N_mo, 1-12
-  core states, 48 imaginary nodes, 16 Pade points): the fp16-split path
-  (FP32-level Pi) with skeleton nodes and the near-real planes of Pi on the
-  FP64 path; the smallest and the largest system against the one-system path
-  bit for bit, every state's residual and Z, and the three smallest systems
-  against the oracle within 1 meV plus the continuation's own uncertainty at
-  the remaining rounding level of W (model_uncertainty).
+  core states, 48 imaginary nodes, 24 Pade points): the fp16-split path
+  (FP32-level Pi and W) at every imaginary node, with the near-real planes
+  of Pi on the FP64 path; the smallest and the largest system against the
+  one-system path bit for bit, every state's residual and Z, and the five
+  smallest systems against the oracle within 1 meV.
 
-With 16 points the continuation of some of these systems is not converged:
-the greedy fit uses every point, CD-WAC is up to 4 meV from full CD, and a
-perturbation of W at the 1e-7 level moves the oracle's own roots by about as
-much.  16-bit Pi at the near-real points leaves W there good to only ~1e-4
-(RPA poles of ~10 Ha within eta_ref = 1e-3 of the points); with those planes
-on the FP64 path, W keeps <= 2e-7 of the state's largest value (the rounding
-of the fp16-split W contraction), and the roots of a converged continuation
-agree with the oracle to 1 meV.
+The Pade set has 24 points (12 near-real, 12 imaginary).  With 16 the
+continuation of some of these systems is not converged: the greedy fit uses
+every point without meeting its tolerance, and a 1e-7 relative perturbation
+of W (the rounding the 16-bit W contraction leaves) moves the oracle's own
+roots by up to 3.9 meV (158-orbital system); with 24 points by at most
+0.29 meV.  16-bit Pi at the near-real points leaves W there good to only
+~1e-4 (RPA poles of ~10 Ha within eta_ref = 1e-3 of the points); with those
+planes on the FP64 path, W keeps <= 2e-7 of the state's largest value.
 """
 import math
 
@@ -44,7 +43,7 @@ def lib():
     c.close()
 
 
-def batch_cases(specs, n_freq=48, n_pade=16):
+def batch_cases(specs, n_freq=48, n_pade=24):
     out = []
     for sp in specs:
         s = synth.make_system(sp["n_mo"], sp["n_occ"], sp["n_aux"], sp["n_core"], sp["sigma"], seed=sp["seed"])
@@ -72,28 +71,6 @@ def same_result(a, b):
         if x["flags"] != y["flags"] or x["n_evals"] != y["n_evals"]:
             return False
     return True
-
-
-def model_uncertainty(case, o, rel=1e-7, trials=3, seed=0):
-    """Largest change of the oracle's QP energies over `trials` draws of a
-    ~rel relative perturbation of every W^c_nm entry, rel being the rounding
-    level of W that the 16-bit modes leave with the near-real planes on the
-    FP64 path.  Small (< 0.02 meV) where the continuation is converged; of
-    the size of CD-WAC's distance from full CD where it is not."""
-    s = case.system
-    q0 = np.array([r[0] for r in o.solve_all()])
-    rng = np.random.default_rng(seed)
-    worst = np.zeros(s.n_states)
-    for _ in range(trials):
-        o2 = cases.oracle(case)
-        o2.w_im = o.w_im * (1 + rel * rng.standard_normal(o.w_im.shape))
-        o2.w_re = o.w_re * (1 + rel * rng.standard_normal(o.w_re.shape))
-        for n in range(s.n_states):
-            m0, m1 = R.fit_range(o2.eps, s.n_occ, o2.win_lo[n] - R.QP_Z_STEP, o2.win_hi[n] + R.QP_Z_STEP)
-            o2.fits[n] = {m: R.thiele_greedy(*o2.reference_data(n, m), o2.pade_tol) for m in range(m0, m1)}
-        q = np.array([r[0] for r in o2.solve_all()])
-        worst = np.maximum(worst, np.abs(q - q0))
-    return worst
 
 
 def test_small_batch_fp64(lib):
@@ -129,15 +106,14 @@ def test_uneven_batch_48_systems(lib):
     from concurrent.futures import ThreadPoolExecutor
     specs = synth.batch_specs()
     order = np.argsort([sp["n_mo"] for sp in specs])
-    small = set(int(j) for j in order[:3])
+    small = set(int(j) for j in order[:5])
     # 72 GB of O^{ia} in all: drawn on 8 threads (one generator per system),
     # moved to the device system by system; only the oracle's three keep a
     # host copy
     systems, params, keep, cs = [], [], [], []
     with ThreadPoolExecutor(8) as ex:
         for j, c in enumerate(ex.map(lambda sp: batch_cases([sp])[0], specs)):
-            sy, pr, kp = descriptors(lib, [c], "f16x3", fit_all=True, freq_rank_tol=1e-10,
-                                     near_real_f64=True)
+            sy, pr, kp = descriptors(lib, [c], "f16x3", fit_all=True, near_real_f64=True)
             systems += sy
             params += pr
             keep += kp
@@ -152,22 +128,38 @@ def test_uneven_batch_48_systems(lib):
     print(f"cdwac_solve_batch: 48 systems in {time.perf_counter() - t:.2f} s", flush=True)
     n_states = sum(c.system.n_states for c in cs)
     assert sum(len(r) for r in res) == n_states == sum(sp["n_core"] for sp in specs)
-    print("states", n_states, "no root:", sum(bool(x["flags"] & R.FLAG_NOROOT) for r in res for x in r))
+    noroot = [(j, n) for j, r in enumerate(res) for n, x in enumerate(r) if x["flags"] & R.FLAG_NOROOT]
+    print("states", n_states, "no root:", noroot, flush=True)
     for j, r in enumerate(res):
         for n, x in enumerate(r):
             if x["flags"] & R.FLAG_NOROOT:
                 continue
             assert abs(x["residual"]) < 1e-8 and 0.0 < x["z"] <= 1.0, (j, n, x)
             assert cs[j].lo[n] <= x["qp"] <= cs[j].hi[n]
+    # what the root search met where it found no root: f on the scan grid
+    for j, n in noroot:
+        lib.cdwac_prepare(systems[j], params[j])
+        xs = np.arange(cs[j].lo[n], cs[j].hi[n], 0.01)
+        om = np.full((cs[j].system.n_states, len(xs)), np.nan)
+        om[:, :] = [np.clip(xs, cs[j].lo[k], cs[j].hi[k]) for k in range(cs[j].system.n_states)]
+        sig = lib.cdwac_sigma(om)[n]
+        one = lib.cdwac_qp(cs[j].system.n_states)[n]
+        e_n = float(cs[j].system.eps[cs[j].system.state_idx[n]])
+        f = xs - e_n - sig + one["sigma_x"]
+        ups = [k for k in range(len(xs) - 1) if f[k] <= 0 < f[k + 1]]
+        print(f"no root: system {j} (N_mo {cs[j].system.n_mo}, {cs[j].system.n_states} cores) state {n}: "
+              f"upward sign changes of f at {[round(xs[k] * synth.HARTREE_EV, 3) for k in ups]} eV with "
+              f"|f| {[(round(abs(f[k]), 4), round(abs(f[k + 1]), 4)) for k in ups]} Ha; "
+              f"core KS levels {np.round(cs[j].system.eps[:cs[j].system.n_states] * synth.HARTREE_EV, 3).tolist()} eV",
+              flush=True)
     for j in (order[0], order[-1]):
         assert same_result(res[j], lib.cdwac_solve(systems[j], params[j])), j
-    for j in order[:3]:
+    for j in order[:5]:
         o = cases.oracle(cs[j])
-        unc = model_uncertainty(cs[j], o)
         for n, r in enumerate(o.solve_all()):
             assert res[j][n]["flags"] & R.FLAG_NOROOT == r[3] & R.FLAG_NOROOT, (j, n)
             if not r[3] & R.FLAG_NOROOT:
                 err = abs(res[j][n]["qp"] - r[0])
-                print(f"system {j} state {n}: {err / MEV:.4f} meV from the oracle, "
-                      f"uncertainty of the continuation {unc[n] / MEV:.4f} meV")
-                assert err <= MEV + unc[n], (j, n, res[j][n]["qp"], r[0], unc[n])
+                print(f"system {j} (N_mo {cs[j].system.n_mo}) state {n}: {err / MEV:.4f} meV from the oracle",
+                      flush=True)
+                assert err <= MEV, (j, n, res[j][n]["qp"], r[0])

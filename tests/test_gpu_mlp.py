@@ -40,8 +40,33 @@ def test_forward_matches_reference(lib):
     np.testing.assert_allclose(y32, y64, rtol=1e-5, atol=1e-5)
 
 
+def gradient_scale(theta, x, t):
+    """Per parameter, the sum over samples of the moduli of its chain-rule
+    terms, with the output residual |y - t| widened by the scale of the
+    output's own computation (|W3| |h2| + |b3| + |W3| (|W2| |h1| + |b2| +
+    |W2| (|W1| |x| + |b1|))), which bounds how far FP32 rounding of the
+    forward pass can move y.  FP32 rounding of the whole gradient stays
+    within a small multiple of u_32 times this scale, element by element."""
+    p = M.unpack(theta)
+    n = len(x)
+    y, (h1, h2) = M.forward(theta, x)
+    a1 = np.abs(x) @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    a2 = np.abs(h1) @ np.abs(p["W2"]).T + np.abs(p["b2"]) + a1 @ np.abs(p["W2"]).T
+    ys = (np.abs(h2) + a2) @ np.abs(p["W3"][0]) + abs(p["b3"][0])
+    ady = (2.0 / n) * (np.abs(y - t) + ys)[:, None]
+    dz2 = (ady @ np.abs(p["W3"])) * np.abs(1.0 - h2 * h2)
+    dz1 = (dz2 @ np.abs(p["W2"])) * np.abs(1.0 - h1 * h1)
+    return np.concatenate([(dz1.T @ np.abs(x)).ravel(), dz1.sum(0), (dz2.T @ np.abs(h1)).ravel(), dz2.sum(0),
+                           (ady.T @ np.abs(h2)).ravel(), ady.sum(0)])
+
+
 @pytest.mark.parametrize("n", [1, 31, 32, 1000, 5003])
 def test_gradient_matches_reference(lib, n):
+    """Element by element: |g - g_ref| <= 64 u_32 times the gradient's own
+    scale (gradient_scale).  Each chain-rule term carries a few FP32
+    roundings (an 8- or 64-term dot product, tanhf, the sample sum); an
+    FP32 emulation of the same backpropagation stays within 0.32 u_32 of
+    the scale here."""
     x, t = data(n, 2)
     theta = M.init_params(4).astype(np.float32).astype(np.float64)
     xf = x.astype(np.float32).astype(np.float64)
@@ -49,7 +74,10 @@ def test_gradient_matches_reference(lib, n):
     loss, g = lib.cdwac_mlp_grad(theta, xf, tf)
     loss_ref, g_ref = M.loss_and_grad(theta, xf, tf)
     assert loss == pytest.approx(loss_ref, rel=1e-5)
-    assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+    bound = 64.0 * 2.0 ** -24 * gradient_scale(theta, xf, tf)
+    over = np.abs(g - g_ref) / bound
+    print(f"n={n}: largest |g - g_ref| / (u_32 scale) = {64.0 * over.max():.3f} (parameter {int(over.argmax())})")
+    assert np.all(over <= 1.0), (int(over.argmax()), float(over.max()))
 
 
 def test_adam_step_matches_reference(lib):

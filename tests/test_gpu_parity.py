@@ -295,6 +295,37 @@ def test_g_energies_sigma_and_qp_fp64(lib, which):
         assert abs(out[n]["qp"] - r[0]) <= 1e-9 * abs(r[0]), (n, out[n]["qp"], r[0])
 
 
+@pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])
+def test_hedin_shifted_g_fp64(lib, which):
+    """cdwac_qp_hedin, G_dH W0 (Sec. 4): the shift dH_n = Re Sigma_n(eps_n) -
+    v^xc_n, fixed before the QP iteration, moves every energy of G and the
+    Fermi level in state n's self-energy.  Against the oracle (which shifts
+    G's energies, where the kernels evaluate the unshifted Sigma at omega -
+    dH), FP64 path: dH_n and the QP energies to 1e-9 relative, flags
+    identical; the shift really moves the roots away from G0W0's."""
+    case = cases.ragged() if which == "ragged" else cases.workload(which)
+    s = case.system
+    o = R.CdwacOracle(s, case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                      eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, fit_all=True)
+    run(lib, case, "p64", fit_all=True)
+    g0w0 = lib.cdwac_qp(s.n_states)
+    out, dh = lib.cdwac_qp_hedin(s.n_states)
+    for n in range(s.n_states):
+        r = o.solve_hedin(n)
+        print(f"{which} state {n}: dH = {dh[n] * synth.HARTREE_EV:.4f} eV, G_dH W0 "
+              f"{out[n]['qp'] * synth.HARTREE_EV:.6f} eV (oracle {r[0] * synth.HARTREE_EV:.6f}), "
+              f"G0W0 {g0w0[n]['qp'] * synth.HARTREE_EV:.6f} eV")
+        assert abs(dh[n] - r[4]) <= 1e-9 * (abs(r[4]) + abs(o.sigma_x[n]))
+        assert out[n]["flags"] == r[3]
+        assert abs(out[n]["qp"] - r[0]) <= 1e-9 * abs(r[0]), (n, out[n]["qp"], r[0])
+        assert abs(out[n]["qp"] - g0w0[n]["qp"]) > 1e-4
+    # without fit_all the shifted residues would miss their models
+    run(lib, case, "p64")
+    with pytest.raises(cdwac_mod().CdwacError) as e:
+        lib.cdwac_qp_hedin(s.n_states)
+    assert e.value.code == cdwac_mod().CDWAC_EINVAL
+
+
 @pytest.mark.parametrize("mode", ["evgw0", "evgw"])
 def test_evgw_two_solves_fp64(lib, mode):
     """cdwac_evgw against the oracle's loop for two QP solves (the second one
