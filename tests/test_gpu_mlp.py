@@ -176,3 +176,24 @@ def test_trained_seed_gain_on_held_out_system(lib):
     acc = np.mean([(o["flags"] & 4) != 0 for o in res[True]])
     print(f"seed: mean evaluations {ev0:.1f} -> {ev1:.1f}, accepted {acc:.2f}, max |dQP| {max(d):.4f} meV")
     assert max(d) <= 1.0
+
+
+def test_zero_network_seed_changes_nothing(lib):
+    """With every weight of the network zero the seed is the plain secant's
+    own step omega_2 (out_mu = 0, out_sd = 1); with mlp_accept = 0 it is
+    never accepted, the secant continues from (omega_1, omega_2) and repeats
+    the plain search's iterates: the same roots, Z and evaluation counts bit
+    for bit, and no state flagged as seeded.  Ragged case, three states."""
+    from paper_2305_15955_amd import cdwac
+    case = cases.ragged()
+    s = case.system
+    sysc, keep = lib.make_system(s)
+    lib.cdwac_mlp_set_model(np.zeros(cdwac.MLP_NPARAM), np.zeros(8), np.ones(8), 0.0, 1.0)
+    res = {}
+    for mlp in (False, True):
+        prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                    prec="p64", use_mlp_seed=mlp, mlp_accept=0.0)
+        res[mlp] = lib.cdwac_solve(sysc, prm)
+    for a, b in zip(res[False], res[True]):
+        assert a["qp"] == b["qp"] and a["z"] == b["z"] and a["n_evals"] == b["n_evals"]
+        assert not b["flags"] & cdwac.FLAG_MLP_ACCEPTED and a["flags"] == b["flags"]

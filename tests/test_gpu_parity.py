@@ -348,6 +348,26 @@ def test_evgw_two_solves_fp64(lib, mode):
     assert [x["flags"] for x in out] == [r[3] for r in res]
 
 
+@pytest.mark.parametrize("prec", ["p64", "b16x3"])
+def test_repeated_solves_are_bitwise_identical(lib, prec):
+    """The path has no order-dependent reduction (no floating-point atomics):
+    two preparations and solves of the same inputs give the same W tables
+    and QP results bit for bit, in the FP64 path and in the bf16 split."""
+    case = cases.ragged()
+    s = case.system
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, prec=prec)
+    runs = []
+    for _ in range(2):
+        out = lib.cdwac_solve(sysc, prm)
+        w_im, w_re, sx, _ = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+        runs.append((out, w_im, w_re))
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    for a, b in zip(runs[0][0], runs[1][0]):
+        assert a == b
+
+
 def test_new_entry_points_reject_bad_arguments(lib):
     """Status codes of the batch, G-energy, evGW and full-CD entry points
     (checked before any launch)."""
