@@ -295,6 +295,19 @@ int cdwac_pade_fit_eval(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const doub
  * Host outputs; either may be NULL. */
 int cdwac_inversion_residual(const cdwac_ctx *ctx, double *worst, int32_t *matrix);
 
+/* cdwac_pade_fit_eval without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results; the coefficients,
+ * nodes and term counts live in a fixed scratch array of the library (one per
+ * device, about 18 MiB, held until the process ends) instead of a per-call
+ * allocation.  Limit: n_fit * n_pts <= 524288 (CDWAC_EINVAL beyond, checked
+ * before any launch).  Every call on a device uses that device's one scratch
+ * array: calls that overlap on one device (several contexts or host threads)
+ * race and must be serialised by the caller.  Synchronous. */
+int cdwac_pade_fit_eval_noalloc(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const double *u,
+                                const double *w, double tol, int32_t n_x, const double *x,
+                                double *out, int32_t *n_terms);
+
 /* Per-stage timing with HIP events recorded on the context's stream around
  * the kernels of each stage (0 = off, the default). */
 int cdwac_set_timing(cdwac_ctx *ctx, int on);

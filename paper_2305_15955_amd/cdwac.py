@@ -97,6 +97,8 @@ _SIGNATURES = {
                                             _f64p, _f64p, _vp, _vp]),
     "cdwac_pade_fit_eval": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_double,
                                            ctypes.c_int32, _vp, _vp, _vp]),
+    "cdwac_pade_fit_eval_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                                   ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp]),
     "cdwac_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cdwac_get_timing": (ctypes.c_int, [_vp, _f64p, ctypes.c_int32]),
     "cdwac_freq_decomposition": (ctypes.c_int, [ctypes.c_int32, _f64p, ctypes.c_double, ctypes.c_double,
@@ -427,6 +429,24 @@ class Cdwac:
         nt = t.empty(nf, dtype=t.int32, device=self.device)
         _check(self.ctx, self.lib.cdwac_pade_fit_eval(self.ctx, nf, npts, _ptr(ud), _ptr(wd), float(tol), nx,
                                                       _ptr(xd), _ptr(out), _ptr(nt)))
+        o = out.cpu().numpy()
+        return o[..., 0] + 1j * o[..., 1], nt.cpu().numpy()
+
+    def cdwac_pade_fit_eval_noalloc(self, u, w, tol, x):
+        """cdwac_pade_fit_eval through the allocation-free entry point (the
+        library's fixed scratch; n_fit * n_pts <= 524288)."""
+        t = self.torch
+
+        def c2(a):
+            a = np.asarray(a, np.complex128)
+            return self._dev(np.stack([a.real, a.imag], axis=-1))
+        nf, npts = np.asarray(u).shape
+        nx = np.asarray(x).shape[1]
+        ud, wd, xd = c2(u), c2(w), c2(x)
+        out = t.empty((nf, nx, 2), dtype=t.float64, device=self.device)
+        nt = t.empty(nf, dtype=t.int32, device=self.device)
+        _check(self.ctx, self.lib.cdwac_pade_fit_eval_noalloc(self.ctx, nf, npts, _ptr(ud), _ptr(wd), float(tol),
+                                                              nx, _ptr(xd), _ptr(out), _ptr(nt)))
         o = out.cpu().numpy()
         return o[..., 0] + 1j * o[..., 1], nt.cpu().numpy()
 

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -16,6 +17,40 @@
 #include "kernels.h"
 
 using namespace cdwac;
+
+// Fixed device scratch of the allocation-free fit entry point
+// (cdwac_pade_fit_eval_noalloc): the coefficients and nodes of up to
+// kNoAllocFitPoints = n_fit * n_pts complex values each, then the term counts
+// of up to kNoAllocFitPoints fits.  One copy per device, kept until the
+// process ends.  Host code never passes this name to a kernel: it is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress.
+namespace {
+constexpr int64_t kNoAllocFitPoints = (int64_t)1 << 19;
+constexpr size_t kNoAllocPlane = sizeof(double) * 2 * (size_t)kNoAllocFitPoints;
+constexpr size_t kNoAllocBytes = 2 * kNoAllocPlane + sizeof(int) * (size_t)kNoAllocFitPoints;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// Device address of `scratch` on each device, looked up once per device
+// (with that device current) by the first context created on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -123,6 +158,8 @@ struct cdwac_ctx {
     // sampled residual of the inversions of the last preparation
     double fact_ratio = 0.0;
     int32_t fact_mat = -1;
+    // device address of the fixed scratch on this context's device
+    char* scratch = nullptr;
 };
 
 namespace {
@@ -655,7 +692,7 @@ int cdwac_ctx_create(cdwac_ctx** out, int device, void* hip_stream) {
         hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess ||
         hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-        ctx->n_cu < 1) {
+        ctx->n_cu < 1 || scratch_address(device, (void**)&ctx->scratch) != hipSuccess || !ctx->scratch) {
         if (ctx->mlp_theta) (void)hipFree(ctx->mlp_theta);
         if (ctx->side) (void)hipStreamDestroy(ctx->side);
         if (ctx->fork) (void)hipEventDestroy(ctx->fork);
@@ -1647,6 +1684,32 @@ int cdwac_pade_fit_eval(cdwac_ctx* ctx, int32_t n_fit, int32_t n_pts, const doub
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(buf);
     if (e != hipSuccess) return fail(ctx, CDWAC_EHIP, "pade fit: %s", hipGetErrorString(e));
+    return CDWAC_OK;
+}
+
+int cdwac_pade_fit_eval_noalloc(cdwac_ctx* ctx, int32_t n_fit, int32_t n_pts, const double* u, const double* w,
+                                double tol, int32_t n_x, const double* x, double* out, int32_t* n_terms) {
+    if (!ctx) return CDWAC_EINVAL;
+    if (n_fit < 0 || n_pts < 1 || n_pts > kMaxPade || n_x < 0 || !(tol >= 0.0))
+        return fail(ctx, CDWAC_EINVAL, "bad fit sizes (n_pts must be in [1, %d])", kMaxPade);
+    if ((int64_t)n_fit * n_pts > kNoAllocFitPoints)
+        return fail(ctx, CDWAC_EINVAL, "n_fit * n_pts = %lld exceeds the fixed scratch (%lld)",
+                    (long long)n_fit * n_pts, (long long)kNoAllocFitPoints);
+    if (n_fit == 0) return CDWAC_OK;
+    if (!u || !w || (n_x > 0 && (!x || !out))) return fail(ctx, CDWAC_EINVAL, "NULL array");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    // every coefficient, node and term count the evaluation reads is written
+    // by the fit kernel of this call, so nothing in the scratch is cleared
+    double* coef = (double*)ctx->scratch;
+    double* node = (double*)(ctx->scratch + kNoAllocPlane);
+    int* nt = (int*)(ctx->scratch + 2 * kNoAllocPlane);
+    launch_thiele_fit(st, n_fit, n_pts, u, w, tol, coef, node, nt);
+    launch_thiele_eval(st, n_fit, n_pts, coef, node, nt, n_x, x, out);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && n_terms) e = hipMemcpyAsync(n_terms, nt, sizeof(int) * n_fit, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ctx, CDWAC_EHIP, "pade fit (fixed scratch): %s", hipGetErrorString(e));
     return CDWAC_OK;
 }
 
