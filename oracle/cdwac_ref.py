@@ -47,6 +47,7 @@ QP_BISECT_TOL = 1e-12     # Ha
 QP_Z_STEP = 1e-4          # Ha, central difference for Z
 QP_F_TOL = 1e-9           # Ha, |f| bound for secant convergence
 QP_ROOT_FTOL = 1e-8       # Ha, |f| bound at a bisected fallback root
+QUAD_GAMMA = 1.0          # Ha, width of the subtracted Lorentzian of the a_m -> 0 limit
 
 FLAG_NOROOT = 1
 FLAG_FALLBACK = 2
@@ -216,15 +217,31 @@ def occupation_factor(eps_m: np.ndarray, eps_f: float, omega: float) -> np.ndarr
 
 
 def integral_term(omega: float, eps: np.ndarray, w_imag: np.ndarray,
-                  freq: np.ndarray, weight: np.ndarray) -> float:
+                  freq: np.ndarray, weight: np.ndarray, w0=None,
+                  gamma: float = QUAD_GAMMA) -> float:
     """I_n(omega) of Eq. (In_term) by quadrature on the imaginary grid.
 
     ``w_imag`` is W^c_nm(i omega_k) as [n_mo, n_freq].  The integrand is
     folded over +-omega' (W even and real there) and eta -> 0.
+
+    With ``w0`` ([n_mo], the value W_nm takes at a_m = 0 in the residue term)
+    the a_m -> 0 limit is taken analytically: the Lorentzian a/(a^2 + w'^2)
+    concentrates at w' = 0 as a_m -> 0, below the grid's smallest node, and
+    the exact integral jumps by W_nm(0) there (the jump the residue term's
+    occupation factor makes in the other direction, Eq. ffact).  The part
+    w0 g(w'), g = gamma^2 / (gamma^2 + w'^2), is integrated in closed form,
+    int_0^inf g a / (a^2 + w'^2) dw' = (pi/2) sgn(a) gamma / (|a| + gamma),
+    and only the remainder, which vanishes at w' = 0, by quadrature.
     """
     a = omega - eps
     kern = a[:, None] / (a[:, None] ** 2 + freq[None, :] ** 2)
-    return float(np.sum(weight[None, :] * w_imag * kern) / math.pi)
+    if w0 is None:
+        return float(np.sum(weight[None, :] * w_imag * kern) / math.pi)
+    w0 = np.asarray(w0, np.float64)
+    g = gamma * gamma / (gamma * gamma + freq * freq)
+    smooth = np.sum(weight[None, :] * (w_imag - w0[:, None] * g[None, :]) * kern) / math.pi
+    limit = np.sum(w0 * 0.5 * np.sign(a) * gamma / (np.abs(a) + gamma))
+    return float(smooth + limit)
 
 
 def residue_term_complex(omega: float, eps: np.ndarray, eps_f: float, eta: float,
@@ -364,8 +381,9 @@ class CdwacOracle:
     def __init__(self, system, freq, weight, ref_im_idx, ref_re, win_lo, win_hi,
                  eta: float = 1e-3, eta_ref: float = 1e-3, pade_tol: float = 1e-9,
                  vxc=None, eps_fermi: Optional[float] = None, fit_all: bool = False,
-                 eps_qp=None):
+                 eps_qp=None, quad_limit: bool = False):
         self.sys = system
+        self.quad_limit = quad_limit
         self.eps = np.asarray(system.eps, np.float64)
         # energies of G in the self-energy (set_g_energies replaces them) and
         # eps_n of the QP equation (the KS energies)
@@ -400,6 +418,21 @@ class CdwacOracle:
                 u, w = self.reference_data(s, m)
                 models[m] = thiele_greedy(u, w, self.pade_tol)
             self.fits.append(models)
+        self.w0 = self.limit_values() if quad_limit else None
+
+    def limit_values(self):
+        """W^c_nm at a_m = 0 as the residue term takes it, Re T_nm((i eta)^2),
+        for every m with a model (0 for the others, whose residue cannot
+        reach the window): [n_states, n_mo]."""
+        w0 = np.zeros((self.sys.n_states, self.sys.n_mo))
+        for s in range(self.sys.n_states):
+            for m in self.fits[s]:
+                w0[s, m] = self.w_model(s, m, 1j * self.eta).real
+        return w0
+
+    def i_term(self, s: int, omega: float, eps_g) -> float:
+        return integral_term(omega, eps_g, self.w_im[s], self.freq, self.weight,
+                             None if self.w0 is None else self.w0[s])
 
     def set_g_energies(self, eps_g, eps_fermi: Optional[float] = None):
         """Orbital energies of G in I_n, R_n and Eq. (ffact); W and its models
@@ -428,7 +461,7 @@ class CdwacOracle:
 
     def sigma(self, s: int, omega: float) -> float:
         """Re Sigma_n(omega) = Sigma^x + Re R - I (Eq. cdselfe), CD-WAC."""
-        i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
+        i_term = self.i_term(s, omega, self.eps_g)
         r_term = residue_term(omega, self.eps_g, self.eps_f, self.eta,
                               lambda m, z: self.w_model(s, m, z))
         return self.sigma_x[s] + r_term - i_term
@@ -438,7 +471,7 @@ class CdwacOracle:
 
     def sigma_complex(self, s: int, omega: float) -> complex:
         """Sigma^x + R - I with the complex residue term."""
-        i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
+        i_term = self.i_term(s, omega, self.eps_g)
         r_term = residue_term_complex(omega, self.eps_g, self.eps_f, self.eta,
                                       lambda m, z: self.w_model(s, m, z))
         return self.sigma_x[s] + r_term - i_term
@@ -464,7 +497,7 @@ class CdwacOracle:
         energy of G and the Fermi level moved by dh (W and its models stay)."""
         eps_g = self.eps_g + dh
         ef = self.eps_f + dh
-        i_term = integral_term(omega, eps_g, self.w_im[s], self.freq, self.weight)
+        i_term = self.i_term(s, omega, eps_g)
         r_term = residue_term(omega, eps_g, ef, self.eta, lambda m, z: self.w_residue(s, m, z))
         return self.sigma_x[s] + r_term - i_term
 
@@ -501,11 +534,15 @@ class FullCdOracle(CdwacOracle):
     """
 
     def __init__(self, system, freq, weight, win_lo, win_hi, eta: float = 1e-3,
-                 vxc=None, eps_fermi: Optional[float] = None, eps_qp=None):
+                 vxc=None, eps_fermi: Optional[float] = None, eps_qp=None,
+                 quad_limit: bool = False):
         super().__init__(system, freq, weight, np.zeros(0, np.int64), np.zeros(0),
                          win_lo, win_hi, eta=eta, eta_ref=eta, pade_tol=0.0,
                          vxc=vxc, eps_fermi=eps_fermi, fit_all=True, eps_qp=eps_qp)
         self._cache = {}
+        self.quad_limit = quad_limit
+        # W^c_nm at the residue point of a_m = 0, i eta, evaluated directly
+        self.w0 = w_table(system, [1j * eta]).real[:, :, 0] if quad_limit else None
 
     def w_residue(self, s: int, m: int, z: complex) -> complex:
         """W^c_nm at a residue point: evaluated directly (full CD)."""
@@ -520,7 +557,7 @@ class FullCdOracle(CdwacOracle):
         return complex(self._cache[key][m])
 
     def sigma(self, s: int, omega: float) -> float:
-        i_term = integral_term(omega, self.eps_g, self.w_im[s], self.freq, self.weight)
+        i_term = self.i_term(s, omega, self.eps_g)
         r_term = residue_term(omega, self.eps_g, self.eps_f, self.eta,
                               lambda m, z: self.w_direct(s, m, z))
         return self.sigma_x[s] + r_term - i_term
