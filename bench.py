@@ -469,6 +469,8 @@ def main():
     res["spectral_peak_ev"] = [float(om[n, int(np.argmax(spec[n]))] * synth.HARTREE_EV) for n in range(s.n_states)]
     res["qp_ev"] = [o["qp"] * synth.HARTREE_EV for o in out]
     res["n_evals_mean"] = float(np.mean([o["n_evals"] for o in out]))
+    res["n_rounds_mean"] = float(np.mean([o["n_rounds"] for o in out]))
+    res["seed_accepted"] = int(sum(bool(o["flags"] & cdwac.FLAG_MLP_ACCEPTED) for o in out))
 
     res["inversion_residual"] = lib.cdwac_inversion_residual()[0]
 
@@ -478,7 +480,8 @@ def main():
         err = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(out, out64)]
         res["fp64_path"] = {"value": s.n_states / dt64, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
                             "warmup": args.fp64_warmup, "stages_ms": st64,
-                            "n_evals_mean": float(np.mean([o["n_evals"] for o in out64]))}
+                            "n_evals_mean": float(np.mean([o["n_evals"] for o in out64])),
+                            "n_rounds_mean": float(np.mean([o["n_rounds"] for o in out64]))}
         res["mev_err_vs_fp64"] = {"max": max(err), "mean": float(np.mean(err)), "per_state": err}
         res["speedup_vs_fp64_path"] = dt64 / dt
 

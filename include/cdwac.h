@@ -134,6 +134,18 @@ typedef struct {
                                   width, so 16-bit Pi leaves W good to only ~1e-4..1e-2
                                   there.  Costs FP64 matrix-core time for 2*n_ref_re planes
                                   and an FP64 copy of O^{ia}.                              */
+    int32_t quad_limit;        /* 1: the integral term I_n takes the a_m = omega - eps_m -> 0
+                                  limit analytically: W_nm(i w') is split into
+                                  w0 g(w') + [W_nm(i w') - w0 g(w')], g = 1 / (1 + w'^2 / Ha^2),
+                                  w0 = Re of the residue term's own W at a_m = 0 (the Pade
+                                  model at i eta), the first part integrated in closed form
+                                  and only the remainder by quadrature.  Without it a
+                                  Lorentzian narrower than the grid's smallest node is
+                                  missed and Sigma_n steps by ~W_nm(0) at omega = eps_m:
+                                  the evGW0 and G_dH W0 roots sit at such a point for the
+                                  state's own m.  Applies to the orbitals with a model (the
+                                  fit range, or every m with fit_all).  0: the plain
+                                  quadrature.  Not supported by cdwac_solve_batch.       */
 } cdwac_params;
 
 /* Result for one state (host, written by cdwac_qp / cdwac_solve). */
@@ -145,6 +157,9 @@ typedef struct {
     double residual;           /* f(qp) = qp - eps_n - Re Sigma_n(qp) + v^xc_n             */
     int32_t n_evals;           /* self-energy evaluations used                             */
     int32_t flags;             /* CDWAC_FLAG_*                                             */
+    int32_t n_rounds;          /* passes over the W tables and fits those evaluations took;
+                                  points evaluated together (the Z pair, the learned seed's
+                                  samples) count once                                      */
 } cdwac_state_out;
 
 /* Context: binds a device and a stream.  hip_stream NULL = the null stream. */
@@ -344,17 +359,20 @@ int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double omega_lo
 
 /* ---- Learned QP seed: MLP 8 -> 64 -> 64 -> 1 (tanh), FP32 ----------------
  * Parameter vector (CDWAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64],
- * b2[64], W3[1][64], b3[1].  The root search evaluates f(w) = w - eps_n -
- * Sigma_n(w) + v^xc_n at w0 = eps_n and w1 = w0 - f(w0), which give the secant
- * step w2.  Features of a state (Ha): eps_n, eps_F, Sigma^x - v^xc,
- * Re Sigma^c(w0), Re Sigma^c(w1), w1 - w0, f(w1), w2 - w1; the network predicts
- * the remaining correction w* - w2, so the seed needs no self-energy
- * evaluation beyond those two.  Inputs are standardised with (mu, sd) and the
- * output is y * out_sd + out_mu.  A seed with |f| <= mlp_accept and a
- * physical Z in (0, 1] is the root (flag CDWAC_FLAG_MLP_ACCEPTED); a seed with
- * |f| <= mlp_accept but Z outside (0, 1] is dropped and the plain search from
- * w0 and w1 runs; otherwise the secant continues from w1 and the seed, and if
- * that search fails the plain one from w0 and w1 runs. */
+ * b2[64], W3[1][64], b3[1].  With use_mlp_seed the root search first
+ * evaluates, in one pass over the tables, f(w) = w - eps_n - Sigma_n(w) +
+ * v^xc_n at the four points w_j = eps_n + d_j, d = (-0.1, -0.05, 0.05, 0.1)
+ * Ha (all four must lie in the window, else the plain search runs).  The
+ * least-squares line through (d_j, f(w_j)) gives w_N = eps_n - mean(f) /
+ * slope (eps_n - mean(f) if the slope is not positive), clamped to the
+ * window.  Features (Ha): eps_n, eps_F, Sigma^x - v^xc, Re Sigma^c(w_0..w_3),
+ * w_N - eps_n; the network predicts the correction w* - w_N.  Inputs are
+ * standardised with (mu, sd) and the output is y * out_sd + out_mu.  A
+ * second pass evaluates f at the seed and at seed +- 1e-4 Ha: the seed is
+ * the root if |f| <= mlp_accept and its Z is in (0, 1] (flag
+ * CDWAC_FLAG_MLP_ACCEPTED, two passes in all); otherwise the secant continues
+ * from the sample nearest the seed and the seed, and if that search fails
+ * the plain one from eps_n runs. */
 #define CDWAC_MLP_NIN 8
 #define CDWAC_MLP_NPARAM 4801
 

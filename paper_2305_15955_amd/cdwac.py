@@ -57,13 +57,13 @@ class CdwacParams(ctypes.Structure):
                 ("qp_tol", ctypes.c_double), ("qp_maxit", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("use_mlp_seed", ctypes.c_int32), ("mlp_accept", ctypes.c_double),
                 ("freq_rank_tol", ctypes.c_double), ("fit_all", ctypes.c_int32),
-                ("near_real_f64", ctypes.c_int32)]
+                ("near_real_f64", ctypes.c_int32), ("quad_limit", ctypes.c_int32)]
 
 
 class CdwacStateOut(ctypes.Structure):
     _fields_ = [("qp", ctypes.c_double), ("z", ctypes.c_double), ("sigma_x", ctypes.c_double),
                 ("sigma_c", ctypes.c_double), ("residual", ctypes.c_double),
-                ("n_evals", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("n_evals", ctypes.c_int32), ("flags", ctypes.c_int32), ("n_rounds", ctypes.c_int32)]
 
 
 class CdwacError(RuntimeError):
@@ -256,7 +256,7 @@ class Cdwac:
     def make_params(freq, weight, ref_im_idx, ref_re, win_lo, win_hi, eta=1e-3, eta_ref=1e-3,
                     pade_tol=1e-9, qp_tol=1e-10, qp_maxit=100, prec="p64", use_mlp_seed=False,
                     mlp_accept=0.0, freq_rank_tol=0.0, fit_all=False,
-                    near_real_f64=False):
+                    near_real_f64=False, quad_limit=False):
         arrs = dict(freq=np.ascontiguousarray(freq, np.float64),
                     weight=np.ascontiguousarray(weight, np.float64),
                     ref_im=np.ascontiguousarray(ref_im_idx, np.int32),
@@ -273,7 +273,7 @@ class Cdwac:
                         qp_maxit=qp_maxit, prec=PREC[prec] if isinstance(prec, str) else int(prec),
                         use_mlp_seed=int(bool(use_mlp_seed)), mlp_accept=mlp_accept,
                         freq_rank_tol=freq_rank_tol, fit_all=int(bool(fit_all)),
-                        near_real_f64=int(bool(near_real_f64)))
+                        near_real_f64=int(bool(near_real_f64)), quad_limit=int(bool(quad_limit)))
         return p, arrs
 
     # -- entry points -----------------------------------------------------
@@ -527,4 +527,4 @@ class Cdwac:
 
 def _outs(out):
     return [dict(qp=o.qp, z=o.z, sigma_x=o.sigma_x, sigma_c=o.sigma_c, residual=o.residual,
-                 n_evals=o.n_evals, flags=o.flags) for o in out]
+                 n_evals=o.n_evals, flags=o.flags, n_rounds=o.n_rounds) for o in out]

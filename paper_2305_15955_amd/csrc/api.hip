@@ -83,7 +83,7 @@ struct Plan {
     int64_t K, kpad;
     // persistent regions
     Region eps, eps_g, freq, weight, ref_re, ref_im, state_idx, vxc, sigx, win_lo, win_hi, m0, m1, fit_off, fit_s,
-        fit_m, w_im, w_re, coef, node, nterm, qpout, err, hedin;
+        fit_m, w_im, w_re, coef, node, nterm, qpout, err, hedin, w0;
     // transient regions (prepare only)
     Region zr, zi, part, idflag, amax, sf, cw, cw64, x64, xh, xl, E, dinv_r, pbuf_r, qbuf_r, dinv_c, pbuf_c, qbuf_c,
         dscr_r, lh, ll,
@@ -107,6 +107,7 @@ struct HostState {
     double mlp_accept = 0.0;
     bool vxc_is_sigx = false;
     bool fit_all = false;
+    bool quad_limit = false;
     // imaginary nodes with a plane (ascending), the others, and the
     // interpolation of W at the others: W_rest[r] = sum_j T[r][j] W_node[j]
     std::vector<int> node, rest;
@@ -259,6 +260,7 @@ int validate_params(cdwac_ctx* ctx, const cdwac_system* s, const cdwac_params* p
     if (p->fit_all != 0 && p->fit_all != 1) return fail(ctx, CDWAC_EINVAL, "fit_all must be 0 or 1");
     if (p->near_real_f64 != 0 && p->near_real_f64 != 1)
         return fail(ctx, CDWAC_EINVAL, "near_real_f64 must be 0 or 1");
+    if (p->quad_limit != 0 && p->quad_limit != 1) return fail(ctx, CDWAC_EINVAL, "quad_limit must be 0 or 1");
     return CDWAC_OK;
 }
 
@@ -477,6 +479,8 @@ Plan make_plan(const cdwac_system* s, const cdwac_params* p, HostState* hs, bool
     add(P, P.qpout, sizeof(QpOut) * P.S);
     // G_dH W0: evaluation points eps_n, Sigma_n(eps_n), shifts dH_n
     add(P, P.hedin, sizeof(double) * 3 * (size_t)P.S);
+    // W at a_m = 0 of every fit (analytic limit of the integral term)
+    add(P, P.w0, sizeof(double) * std::max(P.n_fit, 1));
     add(P, P.err, sizeof(int) * 4);
     // transient
     add(P, P.zr, sizeof(double) * P.n_f);
@@ -672,6 +676,7 @@ QpArgs qp_args(cdwac_ctx* c) {
     }
     a.mlp_out_mu = c->mlp_out_mu;
     a.mlp_out_sd = c->mlp_out_sd;
+    a.w0 = c->hs.quad_limit ? at<double>(c, P.w0) : nullptr;
     return a;
 }
 
@@ -780,6 +785,7 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
     hs.mlp_accept = prm->mlp_accept;
     hs.vxc_is_sigx = sys->vxc == nullptr;
     hs.fit_all = prm->fit_all != 0;
+    hs.quad_limit = prm->quad_limit != 0;
     if (sys->vxc) hs.vxc.assign(sys->vxc, sys->vxc + P.S);
 
     // weight vectors: imaginary nodes, then (Re, Im) of every near-real point
@@ -1028,6 +1034,11 @@ int prepare_impl(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* pr
             launch_thiele_fit(st, P.n_fit, P.n_pts, ru, rw, prm->pade_tol, at<double>(ctx, P.coef),
                               at<double>(ctx, P.node), at<int>(ctx, P.nterm));
             LAUNCHCK();
+            if (hs.quad_limit) {
+                launch_w0_from_fits(st, P.n_fit, P.n_pts, at<double>(ctx, P.coef), at<double>(ctx, P.node),
+                                    at<int>(ctx, P.nterm), prm->eta, at<double>(ctx, P.w0));
+                LAUNCHCK();
+            }
         }
     }
     TRY(seg_end(ctx));
@@ -1199,6 +1210,8 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
         TRY(validate_params(ctx, &sys[j], &prm[j]));
         if (prm[j].use_mlp_seed && !ctx->have_mlp)
             return fail(ctx, CDWAC_EINVAL, "system %d: use_mlp_seed set but no model installed", j);
+        if (prm[j].quad_limit)
+            return fail(ctx, CDWAC_EINVAL, "system %d: quad_limit is not supported in a batch", j);
         const int m = prm[j].n_ref_im + prm[j].n_ref_re;
         if (j == 0) n_pts = m;
         if (m != n_pts || prm[j].pade_tol != prm[0].pade_tol)
@@ -1421,7 +1434,12 @@ int cdwac_sigma_cd(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* 
         rx.push_back(0.0);
     }
     const int nr = (int)rm.size();
-    if (nr > kMaxPade) return fail(ctx, CDWAC_EINVAL, "%d residues exceed the %d near-real planes of one call", nr, kMaxPade);
+    // with the analytic limit one more point, i eta (a_m = 0), gives every
+    // m's W at the residue point of a_m = 0 directly
+    const int n_pts_re = nr + (prm->quad_limit ? 1 : 0);
+    if (n_pts_re > kMaxPade)
+        return fail(ctx, CDWAC_EINVAL, "%d residues exceed the %d near-real planes of one call", nr, kMaxPade);
+    if (prm->quad_limit) rx.push_back(0.0);
     if (n_res) *n_res = rf[0] == 0.0 && nr == 1 ? 0 : nr;
     // one state; the residues are the near-real points (eta_ref = eta); every m fitted
     cdwac_system s1 = *sys;
@@ -1433,7 +1451,7 @@ int cdwac_sigma_cd(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* 
     cdwac_params p1 = *prm;
     p1.n_ref_im = 0;
     p1.ref_im_idx = nullptr;
-    p1.n_ref_re = nr;
+    p1.n_ref_re = n_pts_re;
     p1.ref_re = rx.data();
     p1.eta_ref = prm->eta > 0.0 ? prm->eta : 1e-3;
     p1.win_lo = prm->win_lo + state;
@@ -1450,7 +1468,11 @@ int cdwac_sigma_cd(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* 
     TRY(upload(ctx, (int*)(base + o_rm), rm.data(), nr));
     TRY(upload(ctx, (double*)(base + o_rf), rf.data(), nr));
     const Plan& P = ctx->plan;
-    launch_sigma_direct(st, qp_args(ctx), omega, at<double>(ctx, P.w_re), nr, (const int*)(base + o_rm),
+    if (prm->quad_limit) {
+        launch_w0_from_points(st, P.n_fit, at<double>(ctx, P.w_re), n_pts_re, nr, at<double>(ctx, P.w0));
+        LAUNCHCK();
+    }
+    launch_sigma_direct(st, qp_args(ctx), omega, at<double>(ctx, P.w_re), n_pts_re, nr, (const int*)(base + o_rm),
                         (const double*)(base + o_rf), (double*)(base + o_out));
     LAUNCHCK();
     HIPCK(hipMemcpyAsync(out, base + o_out, sizeof(double) * 3, hipMemcpyDeviceToHost, st));

@@ -20,6 +20,9 @@ namespace cdwac {
 constexpr double kScanStep = 0.01, kScanFmax = 0.1, kBisectTol = 1e-12, kZStep = 1e-4, kFTol = 1e-9,
                  kRootFTol = 1e-8;
 constexpr int kQpThreads = 256, kMaxFreq = 512;
+// Offsets from eps_n (Ha) of the learned seed's four self-energy samples
+// (symmetric: they sum to zero).
+__constant__ const double kSeedOffset[4] = {-0.1, -0.05, 0.05, 0.1};
 constexpr double kPi = 3.14159265358979323846;
 
 __device__ inline double block_sum(double v, double* red) {
@@ -36,62 +39,120 @@ __device__ inline double block_sum(double v, double* red) {
 
 __device__ inline double theta(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? 0.0 : 0.5); }
 
+// Width (Ha) of the Lorentzian g(w') = 1 / (1 + w'^2 / gamma^2) split off in the
+// analytic a_m -> 0 limit of the integral term.
+constexpr double kQuadGamma = 1.0;
+
 struct Shared {
     double red[kQpThreads];
     double freq[kMaxFreq];
     double weight[kMaxFreq];
+    double glor[kMaxFreq];   // g(w_k) of the analytic limit
     float h1[64];
     float h2[64];
 };
 
-// Partial sum of I_n(omega) (Eq. In_term, times pi) over this thread's m.
-__device__ inline double integral_partial(const QpArgs& A, int s, double omega, const Shared& sh) {
+// I_n and R_n of state s at K frequencies in one pass over the tables: every
+// W^c_nm(i w_k) and Pade model is read once and used for all K points, and the
+// K sums are reduced together (one "round" of the root search).  The
+// arithmetic of each point is that of a single evaluation.  A shift dH of
+// every energy of G and of the Fermi level (G_dH W0) enters only through
+// omega - eps_m and eps_F - eps_m, so it is applied as omega - dH.
+template <int K, bool RES = true>
+__device__ void sigma_multi(const QpArgs& A, int s, const double (&omega_in)[K], Shared& sh, double (&I)[K],
+                            double (&R)[K], double* Ri = nullptr) {
+    const double dh = A.g_shift ? A.g_shift[s] : 0.0;
+    double omega[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) omega[j] = A.g_shift ? omega_in[j] - dh : omega_in[j];
     const int nf = A.n_freq;
     const double* W = A.w_im + (int64_t)s * A.n_mo * nf;
-    double isum = 0.0;
-    for (int m = threadIdx.x; m < A.n_mo; m += kQpThreads) {
-        double am = omega - A.eps[m];
-        double am2 = am * am;
-        const double* wm = W + (int64_t)m * nf;
-        double acc = 0.0;
-        for (int k = 0; k < nf; ++k) acc += sh.weight[k] * wm[k] * (am / (am2 + sh.freq[k] * sh.freq[k]));
-        isum += acc;
-    }
-    return isum;
-}
-
-// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).  A
-// shift dH of every energy of G and of the Fermi level (G_dH W0) enters only
-// through omega - eps_m and eps_F - eps_m, so it is applied as omega - dH.
-__device__ void sigma_terms(const QpArgs& A, int s, double omega_in, Shared& sh, double& I, double& R,
-                            double* Ri = nullptr) {
-    const double omega = A.g_shift ? omega_in - A.g_shift[s] : omega_in;
-    const double isum = integral_partial(A, s, omega, sh);
-    double rsum = 0.0, risum = 0.0;
+    double isum[K], rsum[K], risum[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) isum[j] = rsum[j] = risum[j] = 0.0;
     const int m0 = A.m0[s], m1 = A.m1[s], foff = A.fit_off[s];
-    for (int m = m0 + threadIdx.x; m < m1; m += kQpThreads) {
-        double em = A.eps[m];
-        double fm = -theta(A.eps_f - em) * theta(em - omega) + theta(em - A.eps_f) * theta(omega - em);
-        if (fm == 0.0) continue;
+    for (int m = threadIdx.x; m < A.n_mo; m += kQpThreads) {
+        const double em = A.eps[m];
+        double am[K], am2[K], acc[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            am[j] = omega[j] - em;
+            am2[j] = am[j] * am[j];
+            acc[j] = 0.0;
+        }
+        const double* wm = W + (int64_t)m * nf;
+        // the analytic a_m -> 0 limit: w0 g(w') integrated in closed form,
+        // the remainder (zero at w' = 0) by quadrature
+        const double w0 = (A.w0 && m >= m0 && m < m1) ? A.w0[foff + (m - m0)] : 0.0;
+        if (w0 != 0.0) {
+            for (int k = 0; k < nf; ++k) {
+                const double wk = sh.weight[k] * (wm[k] - w0 * sh.glor[k]), f2 = sh.freq[k] * sh.freq[k];
+#pragma unroll
+                for (int j = 0; j < K; ++j) acc[j] += wk * (am[j] / (am2[j] + f2));
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double sg = am[j] > 0.0 ? 1.0 : (am[j] < 0.0 ? -1.0 : 0.0);
+                acc[j] += w0 * (0.5 * kPi) * sg * kQuadGamma / (fabs(am[j]) + kQuadGamma);
+            }
+        } else {
+            for (int k = 0; k < nf; ++k) {
+                const double wk = sh.weight[k] * wm[k], f2 = sh.freq[k] * sh.freq[k];
+#pragma unroll
+                for (int j = 0; j < K; ++j) acc[j] += wk * (am[j] / (am2[j] + f2));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) isum[j] += acc[j];
+    }
+    for (int m = m0 + threadIdx.x; RES && m < m1; m += kQpThreads) {
+        const double em = A.eps[m];
         const int f = foff + (m - m0);
         const double* a = A.coef + (int64_t)f * A.n_pts * 2;
         const double* nd = A.node + (int64_t)f * A.n_pts * 2;
         const int p = A.nterm[f];
-        cplx z = cmk(fabs(em - omega), A.eta);
-        cplx u = z * z;
-        cplx val = cmk(0.0, 0.0);
-        if (p > 0) {
-            cplx t = cmk(1.0, 0.0);
-            for (int q = p - 1; q >= 1; --q)
-                t = cmk(1.0, 0.0) + (cmk(a[2 * q], a[2 * q + 1]) * (u - cmk(nd[2 * q - 2], nd[2 * q - 1]))) / t;
-            val = cmk(a[0], a[1]) / t;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double fm =
+                -theta(A.eps_f - em) * theta(em - omega[j]) + theta(em - A.eps_f) * theta(omega[j] - em);
+            if (fm == 0.0) continue;
+            const cplx z = cmk(fabs(em - omega[j]), A.eta);
+            const cplx u = z * z;
+            cplx val = cmk(0.0, 0.0);
+            if (p > 0) {
+                cplx t = cmk(1.0, 0.0);
+                for (int q = p - 1; q >= 1; --q)
+                    t = cmk(1.0, 0.0) + (cmk(a[2 * q], a[2 * q + 1]) * (u - cmk(nd[2 * q - 2], nd[2 * q - 1]))) / t;
+                val = cmk(a[0], a[1]) / t;
+            }
+            rsum[j] += fm * val.re;
+            risum[j] += fm * val.im;
         }
-        rsum += fm * val.re;
-        risum += fm * val.im;
     }
-    I = block_sum(isum, sh.red) / kPi;
-    R = block_sum(rsum, sh.red);
-    if (Ri) *Ri = block_sum(risum, sh.red);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        I[j] = block_sum(isum[j], sh.red) / kPi;
+        R[j] = block_sum(rsum[j], sh.red);
+        if (Ri) Ri[j] = block_sum(risum[j], sh.red);
+    }
+}
+
+// I_n(omega) and R_n(omega) for state s (Im R_n into *Ri when given).
+__device__ inline void sigma_terms(const QpArgs& A, int s, double omega, Shared& sh, double& I, double& R,
+                                   double* Ri = nullptr) {
+    const double om[1] = {omega};
+    double i1[1], r1[1];
+    sigma_multi<1>(A, s, om, sh, i1, r1, Ri);
+    I = i1[0];
+    R = r1[0];
+}
+
+// The integral term alone (full CD adds the directly evaluated residues).
+__device__ inline double integral_only(const QpArgs& A, int s, double omega, Shared& sh) {
+    const double om[1] = {omega};
+    double i1[1], r1[1];
+    sigma_multi<1, false>(A, s, om, sh, i1, r1);
+    return i1[0];
 }
 
 __device__ inline double sigma_total(const QpArgs& A, int s, double omega, Shared& sh) {
@@ -132,31 +193,40 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
     for (int k = threadIdx.x; k < A.n_freq; k += kQpThreads) {
         sh.freq[k] = A.freq[k];
         sh.weight[k] = A.weight[k];
+        sh.glor[k] = kQuadGamma * kQuadGamma / (kQuadGamma * kQuadGamma + A.freq[k] * A.freq[k]);
     }
     __syncthreads();
     const double e_n = A.eps_n[A.state_idx[s]];
     const double vxc = A.vxc[s];
+    const double sx = A.sigx[s];
     const double lo = A.win_lo[s], hi = A.win_hi[s];
-    int n_eval = 0, flags = 0;
+    // n_eval counts self-energy evaluations, n_round the passes over the
+    // tables they took (points evaluated together count once)
+    int n_eval = 0, n_round = 0, flags = 0;
     auto f = [&](double x) {
         ++n_eval;
+        ++n_round;
         return x - e_n - sigma_total(A, s, x, sh) + vxc;
     };
+    // f at K points in one pass
+    auto f_multi = [&](auto& xs, auto& fs) {
+        constexpr int K = sizeof(xs) / sizeof(double);
+        double I[K], R[K];
+        sigma_multi<K>(A, s, xs, sh, I, R);
+#pragma unroll
+        for (int j = 0; j < K; ++j) fs[j] = xs[j] - e_n - (sx + R[j] - I[j]) + vxc;
+        n_eval += K;
+        ++n_round;
+    };
     auto z_factor = [&](double x) {
-        double fp = f(x + kZStep);
-        double fm = f(x - kZStep);
-        return 2.0 * kZStep / (fp - fm);
+        const double xs[2] = {x + kZStep, x - kZStep};
+        double fs[2];
+        f_multi(xs, fs);
+        return 2.0 * kZStep / (fs[0] - fs[1]);
     };
 
     double root = 0.0, zf = 0.0;
     bool done = false;
-    // secant from omega_0 = eps_n and one fixed-point step
-    double w0 = e_n, f0 = f(w0), w1 = w0 - f0, f1 = 0.0;
-    bool in1 = lo <= w1 && w1 <= hi, have_f1 = false;
-    if (in1) {
-        f1 = f(w1);
-        have_f1 = true;
-    }
     // secant iteration from the pair (xa, fa), (xb, fb); on convergence with a
     // physical Z factor the root and Z are taken
     auto secant = [&](double xa, double fa, double xb, double fb) {
@@ -181,38 +251,60 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
         zf = z;
         return true;
     };
-    if (A.use_mlp && in1) {
-        // learned seed: from the two evaluations above (Sigma^c at eps_n and at
-        // omega_1) and the secant step they give, the network predicts the
-        // remaining correction omega* - omega_2
-        const double sx = A.sigx[s];
-        const double sc0 = w0 - e_n + vxc - f0 - sx, sc1 = w1 - e_n + vxc - f1 - sx;
-        const double w2 = f1 != f0 ? w1 - f1 * (w1 - w0) / (f1 - f0) : w1;
-        const double raw[8] = {e_n, A.eps_f, sx - vxc, sc0, sc1, w1 - w0, f1, w2 - w1};
+    if (A.use_mlp && lo <= e_n + kSeedOffset[0] && e_n + kSeedOffset[3] <= hi) {
+        // learned seed: round 1 evaluates Sigma^c at four fixed offsets from
+        // eps_n; the straight line fitted through f there gives a Newton-like
+        // estimate w_N, and the network predicts the remaining correction
+        // w* - w_N from eps_n, eps_F, Sigma^x - v^xc, the four Sigma^c values
+        // and w_N - eps_n.  Round 2 evaluates f at the seed and at seed +- h:
+        // the seed is the root if |f| <= mlp_accept and Z is in (0, 1].
+        double xs[4], fs[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xs[j] = e_n + kSeedOffset[j];
+        f_multi(xs, fs);
+        double sdd = 0.0, sdf = 0.0, sf = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sdd += kSeedOffset[j] * kSeedOffset[j];
+            sdf += kSeedOffset[j] * fs[j];
+            sf += fs[j];
+        }
+        const double slope = sdf / sdd, mean = 0.25 * sf;      // the offsets sum to zero
+        double wn = slope > 0.0 ? e_n - mean / slope : e_n - mean;
+        wn = fmin(fmax(wn, lo), hi);
+        double raw[8] = {e_n, A.eps_f, sx - vxc, 0.0, 0.0, 0.0, 0.0, wn - e_n};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) raw[3 + j] = xs[j] - e_n + vxc - fs[j] - sx;   // Sigma^c(x_j)
         float feat[8];
         for (int i = 0; i < 8; ++i) feat[i] = (float)((raw[i] - A.mlp_mu[i]) / A.mlp_sd[i]);
         const float y = mlp_one(A.mlp_theta, feat, sh);
-        const double seed = w2 + (double)y * A.mlp_out_sd + A.mlp_out_mu;
-        if (seed >= lo && seed <= hi) {
-            const double fs = f(seed);
-            if (fabs(fs) <= A.mlp_accept) {
-                // the same physical-Z test as a secant root: a seed on an
-                // unphysical crossing falls through to the plain search
-                const double z = z_factor(seed);
-                if (0.0 < z && z <= 1.0) {
-                    root = seed;
-                    zf = z;
-                    flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
-                    done = true;
-                }
+        const double seed = wn + (double)y * A.mlp_out_sd + A.mlp_out_mu;
+        if (seed - kZStep >= lo && seed + kZStep <= hi) {
+            const double ps[3] = {seed, seed + kZStep, seed - kZStep};
+            double pf[3];
+            f_multi(ps, pf);
+            const double z = 2.0 * kZStep / (pf[1] - pf[2]);
+            if (fabs(pf[0]) <= A.mlp_accept && 0.0 < z && z <= 1.0) {
+                root = seed;
+                zf = z;
+                flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
+                done = true;
             } else {
-                // the secant continues from omega_1 and the seed
-                done = secant(w1, f1, seed, fs);
+                // the secant continues from the sample nearest the seed and the seed
+                int jn = 0;
+#pragma unroll
+                for (int j = 1; j < 4; ++j)
+                    if (fabs(xs[j] - seed) < fabs(xs[jn] - seed)) jn = j;
+                done = secant(xs[jn], fs[jn], seed, pf[0]);
             }
         }
     }
-    // the plain search from omega_0 and omega_1 (also where a seeded search failed)
-    if (!done && have_f1) done = secant(w0, f0, w1, f1);
+    // the plain search from omega_0 = eps_n and omega_1 = omega_0 - f(omega_0)
+    // (also where a seeded search failed)
+    if (!done) {
+        const double w0 = e_n, f0 = f(w0), w1 = w0 - f0;
+        if (lo <= w1 && w1 <= hi) done = secant(w0, f0, w1, f(w1));
+    }
     if (!done) {
         flags |= CDWAC_FLAG_FALLBACK_DEV;
         const int n = (int)ceil((hi - lo) / kScanStep);
@@ -264,6 +356,7 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
         o.residual = (flags & CDWAC_FLAG_NOROOT_DEV) ? nan("") : root - e_n - (A.sigx[s] + R - I) + vxc;
         o.n_evals = n_eval;
         o.flags = flags;
+        o.n_rounds = n_round;
         *dst = o;
     }
 }
@@ -291,6 +384,7 @@ __global__ __launch_bounds__(kQpThreads) void k_sigma_eval(QpArgs A, int n_omega
     for (int q = threadIdx.x; q < A.n_freq; q += kQpThreads) {
         sh.freq[q] = A.freq[q];
         sh.weight[q] = A.weight[q];
+        sh.glor[q] = kQuadGamma * kQuadGamma / (kQuadGamma * kQuadGamma + A.freq[q] * A.freq[q]);
     }
     __syncthreads();
     const int64_t o = (int64_t)s * n_omega + k;
@@ -316,6 +410,7 @@ __global__ __launch_bounds__(kQpThreads) void k_spectral_eval(QpArgs A, int n_om
     for (int q = threadIdx.x; q < A.n_freq; q += kQpThreads) {
         sh.freq[q] = A.freq[q];
         sh.weight[q] = A.weight[q];
+        sh.glor[q] = kQuadGamma * kQuadGamma / (kQuadGamma * kQuadGamma + A.freq[q] * A.freq[q]);
     }
     __syncthreads();
     const int64_t o = (int64_t)s * n_omega + k;
@@ -337,19 +432,20 @@ __global__ __launch_bounds__(kQpThreads) void k_spectral_eval(QpArgs A, int n_om
 // + i eta) is column fit rm[j] (every m fitted) at near-real point j of w_re.
 // out = {Sigma, R_n, I_n}.
 __global__ __launch_bounds__(kQpThreads) void k_sigma_direct(QpArgs A, double omega, const double* __restrict__ w_re,
-                                                             int n_re, const int* __restrict__ rm,
+                                                             int stride, int n_res, const int* __restrict__ rm,
                                                              const double* __restrict__ rf, double* __restrict__ out) {
     __shared__ Shared sh;
     for (int k = threadIdx.x; k < A.n_freq; k += kQpThreads) {
         sh.freq[k] = A.freq[k];
         sh.weight[k] = A.weight[k];
+        sh.glor[k] = kQuadGamma * kQuadGamma / (kQuadGamma * kQuadGamma + A.freq[k] * A.freq[k]);
     }
     __syncthreads();
-    const double I = block_sum(integral_partial(A, 0, omega, sh), sh.red) / kPi;
+    const double I = integral_only(A, 0, omega, sh);
     double rsum = 0.0;
-    for (int j = threadIdx.x; j < n_re; j += kQpThreads) {
+    for (int j = threadIdx.x; j < n_res; j += kQpThreads) {
         const int f = A.fit_off[0] + (rm[j] - A.m0[0]);
-        rsum += rf[j] * w_re[((int64_t)f * n_re + j) * 2];
+        rsum += rf[j] * w_re[((int64_t)f * stride + j) * 2];
     }
     const double R = block_sum(rsum, sh.red);
     if (threadIdx.x == 0) {
@@ -359,9 +455,9 @@ __global__ __launch_bounds__(kQpThreads) void k_sigma_direct(QpArgs A, double om
     }
 }
 
-void launch_sigma_direct(hipStream_t s, const QpArgs& a, double omega, const double* w_re, int n_re, const int* rm,
-                         const double* rf, double* out) {
-    hipLaunchKernelGGL(k_sigma_direct, dim3(1), dim3(kQpThreads), 0, s, a, omega, w_re, n_re, rm, rf, out);
+void launch_sigma_direct(hipStream_t s, const QpArgs& a, double omega, const double* w_re, int stride, int n_res,
+                         const int* rm, const double* rf, double* out) {
+    hipLaunchKernelGGL(k_sigma_direct, dim3(1), dim3(kQpThreads), 0, s, a, omega, w_re, stride, n_res, rm, rf, out);
 }
 
 int qp_max_freq() { return kMaxFreq; }

@@ -165,6 +165,45 @@ __global__ void k_thiele_eval(int n_fit, int n_pts, const double* __restrict__ c
     out[2 * t + 1] = r.im;
 }
 
+// w0[f] = Re T_f(u) at u = (i eta)^2 = -eta^2: the value the residue term
+// takes for a_m = 0, which the integral term's analytic limit needs.
+__global__ void k_w0_from_fits(int n_fit, int n_pts, const double* __restrict__ coef,
+                               const double* __restrict__ node, const int* __restrict__ nterm, double eta,
+                               double* __restrict__ w0) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_fit) return;
+    const cplx u = cmk(-eta * eta, 0.0);
+    const double* a = coef + (int64_t)f * n_pts * 2;
+    const double* nd = node + (int64_t)f * n_pts * 2;
+    const int p = nterm[f];
+    cplx r = cmk(0.0, 0.0);
+    if (p > 0) {
+        cplx t = cmk(1.0, 0.0);
+        for (int q = p - 1; q >= 1; --q)
+            t = cmk(1.0, 0.0) + (cmk(a[2 * q], a[2 * q + 1]) * (u - cmk(nd[2 * q - 2], nd[2 * q - 1]))) / t;
+        r = cmk(a[0], a[1]) / t;
+    }
+    w0[f] = r.re;
+}
+
+__global__ void k_w0_from_points(int n_fit, const double* __restrict__ w_re, int stride, int j,
+                                 double* __restrict__ w0) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < n_fit) w0[f] = w_re[((int64_t)f * stride + j) * 2];
+}
+
+void launch_w0_from_fits(hipStream_t s, int n_fit, int n_pts, const double* coef, const double* node, const int* nterm,
+                         double eta, double* w0) {
+    if (n_fit > 0)
+        hipLaunchKernelGGL(k_w0_from_fits, dim3((n_fit + 255) / 256), dim3(256), 0, s, n_fit, n_pts, coef, node, nterm,
+                           eta, w0);
+}
+
+void launch_w0_from_points(hipStream_t s, int n_fit, const double* w_re, int stride, int j, double* w0) {
+    if (n_fit > 0)
+        hipLaunchKernelGGL(k_w0_from_points, dim3((n_fit + 255) / 256), dim3(256), 0, s, n_fit, w_re, stride, j, w0);
+}
+
 // Reference data of every fit: imaginary nodes first (u = -omega^2, W real),
 // then the near-real points (u = (x + i eta_ref)^2, W complex).
 __global__ void k_gather_refs(int n_fit, const int* __restrict__ fit_s, const int* __restrict__ fit_m,

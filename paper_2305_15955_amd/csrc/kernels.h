@@ -32,6 +32,7 @@ struct QpArgs {
     const double* win_lo;    // [S]
     const double* win_hi;    // [S]
     const double* g_shift;   // [S] shift of G's energies per state (G_dH W0), or nullptr
+    const double* w0;        // [n_fit] W_nm at a_m = 0 for the analytic limit of I_n, or nullptr
     double eta, eps_f, qp_tol;
     int qp_maxit;
     int use_mlp;
@@ -43,7 +44,7 @@ struct QpArgs {
 
 struct QpOut {
     double qp, z, sigma_x, sigma_c, residual;
-    int32_t n_evals, flags;
+    int32_t n_evals, flags, n_rounds;
 };
 
 // precision codes (same values as cdwac_prec)
@@ -117,14 +118,19 @@ void launch_thiele_fit(hipStream_t s, int n_fit, int n_pts, const double* u, con
                        double* coef, double* node, int* nterm);
 void launch_thiele_eval(hipStream_t s, int n_fit, int n_pts, const double* coef, const double* node,
                         const int* nterm, int n_x, const double* x, double* out);
+// w0[f] = Re T_f((i eta)^2), the model's value at the residue point of a_m = 0
+void launch_w0_from_fits(hipStream_t s, int n_fit, int n_pts, const double* coef, const double* node, const int* nterm,
+                         double eta, double* w0);
+// w0[f] = Re w_re[f][j] (near-real point j of every fit)
+void launch_w0_from_points(hipStream_t s, int n_fit, const double* w_re, int stride, int j, double* w0);
 void launch_gather_refs(hipStream_t s, int n_fit, const int* fit_s, const int* fit_m, int n_mo, int n_freq,
                         const double* w_im, const double* w_re, const double* freq, const int* ref_im_idx,
                         int n_im, const double* ref_re, int n_re, double eta_ref, double* u, double* w);
 
 // k_qp.hip
 int qp_max_freq();
-void launch_sigma_direct(hipStream_t s, const QpArgs& a, double omega, const double* w_re, int n_re, const int* rm,
-                         const double* rf, double* out);
+void launch_sigma_direct(hipStream_t s, const QpArgs& a, double omega, const double* w_re, int stride, int n_res,
+                         const int* rm, const double* rf, double* out);
 void launch_qp_batch(hipStream_t s, int n_blocks, const QpArgs* args, const int2* map, QpOut* out);
 void launch_qp(hipStream_t s, const QpArgs& a, QpOut* out);
 void launch_sigma(hipStream_t s, const QpArgs& a, int n_omega, const double* omega, double* sigma,

@@ -99,7 +99,7 @@ void check_plan(const Plan& P, const char* what) {
                             &P.dinv_r, &P.pbuf_r, &P.qbuf_r, &P.dinv_c, &P.pbuf_c, &P.qbuf_c, &P.dscr_r, &P.lh,
                             &P.ll, &P.bt64, &P.bh, &P.bl, &P.bf64, &P.bfh, &P.bfl, &P.partial_im, &P.partial_re,
                             &P.rowsel, &P.ref_u, &P.ref_w, &P.x32, &P.yh, &P.yl, &P.t_pi, &P.t_w, &P.t_wf,
-                            &P.pmap, &P.imnode, &P.imrest, &P.tmat, &P.rowsum, &P.fcols, &P.fcolidx, &P.fres};
+                            &P.pmap, &P.imnode, &P.imrest, &P.tmat, &P.rowsum, &P.fcols, &P.fcolidx, &P.fres, &P.w0};
     std::vector<std::pair<size_t, size_t>> iv;
     for (const Region* r : regs) {
         if (r->bytes == 0) continue;

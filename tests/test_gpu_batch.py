@@ -102,6 +102,16 @@ def test_batch_rejects_mixed_pade_sizes(lib):
     assert e.value.code == cdwac.CDWAC_EINVAL
 
 
+def test_batch_rejects_quad_limit(lib):
+    from paper_2305_15955_amd import cdwac
+    specs = [dict(n_mo=40, n_occ=7, n_aux=132, n_core=2, sigma=0.03, seed=1)]
+    cs = batch_cases(specs, n_freq=32)
+    systems, params, keep = descriptors(lib, cs, "p64", quad_limit=True)
+    with pytest.raises(cdwac.CdwacError) as e:
+        lib.cdwac_solve_batch(systems, params)
+    assert e.value.code == cdwac.CDWAC_EINVAL
+
+
 def test_uneven_batch_48_systems(lib):
     from concurrent.futures import ThreadPoolExecutor
     specs = synth.batch_specs()

@@ -154,16 +154,17 @@ def test_seed_on_an_unphysical_crossing_falls_back(lib):
     xb = float(xs[bad[np.argmax(viol)]])
     print(f"{len(bad)} grid points with |f| < 0.11 Ha and Z outside (0, 1]; seed at Z = "
           f"{z[bad[np.argmax(viol)]]:.4f}, f = {f[bad[np.argmax(viol)]]:.4f} Ha")
-    # w2: the secant step of the root search's first two evaluations
-    f0 = e_n - e_n - lib.cdwac_sigma(np.array([[e_n]]))[0, 0] + vxc
-    w1 = e_n - f0
-    f1 = w1 - e_n - lib.cdwac_sigma(np.array([[w1]]))[0, 0] + vxc
-    w2 = w1 - f1 * (w1 - e_n) / (f1 - f0)
-    lib.cdwac_mlp_set_model(np.zeros(cd().MLP_NPARAM), np.zeros(8), np.ones(8), xb - w2, 1.0)
+    # w_N: the line estimate of the seed's four samples (the network adds
+    # out_mu to it when every weight is zero)
+    d = np.array([-0.1, -0.05, 0.05, 0.1])
+    fs = (e_n + d) - e_n - lib.cdwac_sigma((e_n + d)[None, :])[0] + vxc
+    slope, mean = float(np.dot(d, fs) / np.dot(d, d)), float(fs.mean())
+    wn = min(max(e_n - mean / slope if slope > 0.0 else e_n - mean, case.lo[0]), case.hi[0])
+    lib.cdwac_mlp_set_model(np.zeros(cd().MLP_NPARAM), np.zeros(8), np.ones(8), xb - wn, 1.0)
     prm, arrs = params(lib, case, prec="p64", use_mlp_seed=True, mlp_accept=0.12)
     got = lib.cdwac_solve(sysc, prm)[0]
     print(f"seed at {xb:.6f} Ha; plain root {plain['qp']:.12f}, seeded search {got['qp']:.12f}, "
-          f"flags {got['flags']}, evaluations {got['n_evals']} (plain {plain['n_evals']})")
+          f"flags {got['flags']}, passes {got['n_rounds']} (plain {plain['n_rounds']})")
     assert not got["flags"] & cd().FLAG_MLP_ACCEPTED
-    assert got["qp"] == plain["qp"] and 0.0 < got["z"] <= 1.0
-    assert got["n_evals"] == plain["n_evals"] + 3      # f(seed) and the two Z evaluations
+    assert abs(got["qp"] - plain["qp"]) <= 1e-9 * abs(plain["qp"]) and 0.0 < got["z"] <= 1.0
+    assert got["n_rounds"] >= 3          # the samples, the seed's pass, then the search

@@ -107,12 +107,12 @@ def test_training_reduces_loss(lib):
     assert loss1 < 0.1 * loss0
 
 
-def test_seed_saves_evaluations_when_accepted(lib):
-    """The seed is built from the root search's first two evaluations, so an
-    accepted seed (|f| <= 1 meV) ends the search after one more (5 with the Z
-    factor, against 8 for the plain secant on this system), and a rejected one
-    costs at most one extra.  Held-out 60-orbital system, v^xc shifted over
-    +-0.3 Ha: fewer evaluations in total, the same roots within 1 meV."""
+def test_seed_saves_rounds_when_accepted(lib):
+    """The seed takes one pass over the tables (Sigma at four points around
+    eps_n); an accepted seed (|f| <= 1 meV, Z in (0, 1]) ends the search
+    after one more (f at the seed and its Z pair): 2 passes, against 6-7 for
+    the plain secant.  Held-out 60-orbital system, v^xc shifted over +-0.3
+    Ha: fewer passes in total, the same roots within 1 meV."""
     mdl = np.load(MODEL)
     lib.cdwac_mlp_set_model(mdl["theta"], mdl["mu"], mdl["sd"], float(mdl["out_mu"]), float(mdl["out_sd"]))
     case = cases.workload("fp64_1core_nmo60")
@@ -127,37 +127,40 @@ def test_seed_saves_evaluations_when_accepted(lib):
         rows = []
         for sh in (-0.3, -0.2, -0.12, -0.06, 0.0, 0.06, 0.12, 0.2, 0.3):
             out = lib.cdwac_qp(s.n_states, vxc=sx + sh)
-            rows.append([(o["qp"], o["n_evals"], o["flags"]) for o in out])
+            rows.append([(o["qp"], o["n_rounds"], o["flags"]) for o in out])
         tot[mlp] = rows
     plain = sum(r[1] for row in tot[False] for r in row)
     seeded = sum(r[1] for row in tot[True] for r in row)
     accepted = sum(bool(r[2] & 4) for row in tot[True] for r in row)
-    print(f"evaluations plain {plain}, seeded {seeded}, seed accepted {accepted} of {len(tot[True])}")
+    print(f"passes plain {plain}, seeded {seeded}, seed accepted {accepted} of {len(tot[True])}")
     for row0, row1 in zip(tot[False], tot[True]):
         for (q0, n0, f0), (q1, n1, f1) in zip(row0, row1):
             assert abs(q1 - q0) <= 1.0e-3 / synth.HARTREE_EV
-            assert n1 <= n0 + 1 and (not f1 & 4 or n1 == 5)
+            assert not f1 & 4 or n1 == 2
     assert accepted >= 1 and seeded < plain
 
 
 def test_seed_on_held_out_systems_of_the_training_recipe(lib):
     """Systems of the training recipe with seeds training never used: every
     seeded root within 1 meV of the plain one and none lost (a failed seeded
-    search falls back to the plain one), fewer evaluations than the plain
-    full-tolerance secant.  Also reported, not asserted: the network-free
-    early stop at omega_2 with the same 1 meV tolerance, which on these
-    systems needs fewer evaluations than the seed."""
+    search falls back to the plain one), and fewer passes over the tables
+    than both the plain full-tolerance secant and the network-free early
+    stop at omega_2 with the same 1 meV tolerance (each charged its most
+    favourable count).  Also reported, not asserted: the network-free
+    estimate from the line through the same four samples."""
     from paper_2305_15955_amd import seed_train
     rows = seed_train.held_out_evaluations(lib, dict(np.load(MODEL)), n_systems=12, max_mo=300)
-    plain, seeded, stop2 = rows[:, 0].sum(), rows[:, 1].sum(), rows[:, 4].sum()
-    print(f"{len(rows)} states: evaluations plain {plain:.0f}, seeded {seeded:.0f} "
-          f"(accepted {rows[:, 2].mean():.2f}), early stop at omega_2 {stop2:.0f}")
+    plain, seeded, stop2, line = rows[:, 0].sum(), rows[:, 1].sum(), rows[:, 4].sum(), rows[:, 5].sum()
+    print(f"{len(rows)} states: passes plain {plain:.0f}, seeded {seeded:.0f} "
+          f"(accepted {rows[:, 2].mean():.2f}), early stop at omega_2 {stop2:.0f}, "
+          f"line estimate of the four samples {line:.0f}")
     assert np.all(np.isfinite(rows[:, 3])) and rows[:, 3].max() <= 1.0e-3 / synth.HARTREE_EV
-    assert seeded < plain
+    assert seeded < min(plain, stop2)
 
 
 def test_trained_seed_gain_on_held_out_system(lib):
-    """Same QP energies (<= 1 meV) with and without the seed; report evaluations."""
+    """Same QP energies (<= 1 meV) with and without the seed on the
+    600-orbital workload; report the passes."""
     assert os.path.exists(MODEL), "seed_model.npz missing (python -m paper_2305_15955_amd.seed_train)"
     mdl = np.load(MODEL)
     lib.cdwac_mlp_set_model(mdl["theta"], mdl["mu"], mdl["sd"], float(mdl["out_mu"]), float(mdl["out_sd"]))
@@ -171,19 +174,19 @@ def test_trained_seed_gain_on_held_out_system(lib):
         lib.cdwac_prepare(sysc, prm)
         res[mlp] = lib.cdwac_qp(s.n_states)
     d = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(res[False], res[True])]
-    ev0 = np.mean([o["n_evals"] for o in res[False]])
-    ev1 = np.mean([o["n_evals"] for o in res[True]])
+    r0 = np.mean([o["n_rounds"] for o in res[False]])
+    r1 = np.mean([o["n_rounds"] for o in res[True]])
     acc = np.mean([(o["flags"] & 4) != 0 for o in res[True]])
-    print(f"seed: mean evaluations {ev0:.1f} -> {ev1:.1f}, accepted {acc:.2f}, max |dQP| {max(d):.4f} meV")
+    print(f"seed: mean passes {r0:.1f} -> {r1:.1f}, accepted {acc:.2f}, max |dQP| {max(d):.4f} meV")
     assert max(d) <= 1.0
 
 
 def test_zero_network_seed_changes_nothing(lib):
-    """With every weight of the network zero the seed is the plain secant's
-    own step omega_2 (out_mu = 0, out_sd = 1); with mlp_accept = 0 it is
-    never accepted, the secant continues from (omega_1, omega_2) and repeats
-    the plain search's iterates: the same roots, Z and evaluation counts bit
-    for bit, and no state flagged as seeded.  Ragged case, three states."""
+    """With every weight of the network zero the seed is the line estimate
+    w_N of the four samples (out_mu = 0, out_sd = 1); with mlp_accept = 0 it
+    is never accepted, and the secant continued from it reaches the roots of
+    the plain search (1e-9 relative), with the same flags and no state
+    flagged as seeded.  Ragged case, three states."""
     from paper_2305_15955_amd import cdwac
     case = cases.ragged()
     s = case.system
@@ -195,5 +198,5 @@ def test_zero_network_seed_changes_nothing(lib):
                                     prec="p64", use_mlp_seed=mlp, mlp_accept=0.0)
         res[mlp] = lib.cdwac_solve(sysc, prm)
     for a, b in zip(res[False], res[True]):
-        assert a["qp"] == b["qp"] and a["z"] == b["z"] and a["n_evals"] == b["n_evals"]
+        assert abs(a["qp"] - b["qp"]) <= 1e-9 * abs(a["qp"]) and abs(a["z"] - b["z"]) <= 1e-6
         assert not b["flags"] & cdwac.FLAG_MLP_ACCEPTED and a["flags"] == b["flags"]

@@ -368,6 +368,90 @@ def test_repeated_solves_are_bitwise_identical(lib, prec):
         assert a == b
 
 
+@pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])
+def test_quad_limit_sigma_next_to_residues_fp64(lib, which):
+    """The analytic a_m -> 0 limit of the integral term (quad_limit): Sigma at
+    omega = eps_n + d with |d| down to 1e-5 Ha, where the plain quadrature
+    steps by ~W_nn(0), against the oracle with the same limit, FP64 path:
+    1e-9 of |Sigma^x| + |Sigma|; and Sigma is continuous across eps_n (the
+    two sides of the step differ by less than 1e-4 of it)."""
+    case = cases.ragged() if which == "ragged" else cases.workload(which)
+    s = case.system
+    o = R.CdwacOracle(s, case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                      eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, fit_all=True, quad_limit=True)
+    run(lib, case, "p64", fit_all=True, quad_limit=True)
+    ds = np.array([-1e-2, -1e-4, -1e-5, 1e-5, 1e-4, 1e-2])
+    oms = np.array([[s.eps[s.state_idx[n]] + d for d in ds] for n in range(s.n_states)])
+    sig = lib.cdwac_sigma(oms)
+    for n in range(s.n_states):
+        for k in range(len(ds)):
+            ref = o.sigma(n, oms[n, k])
+            assert abs(sig[n, k] - ref) <= 1e-9 * (abs(ref) + abs(o.sigma_x[n])), (n, k, sig[n, k], ref)
+        step = abs(sig[n, 3] - sig[n, 2])
+        assert step < 1e-4 * abs(sig[n, 2] - o.sigma_x[n]) + 1e-6, (n, step)
+
+
+@pytest.mark.parametrize("mode", ["evgw0", "evgw"])
+def test_evgw_converges_with_quad_limit_fp64(lib, mode):
+    """With the analytic limit the eigenvalue loops of a core state converge
+    (the state's own G pole sits at its QP energy, where the plain quadrature
+    steps): cdwac_evgw to 1e-9 Ha against the oracle's loop with the same
+    limit, FP64 path, both converged in the same number of solves (< 30),
+    energies to 1e-8 relative, Z ~ 0.9."""
+    case = cases.workload("fp64_1core_nmo60")
+    s = case.system
+    make = lambda sw, ks: R.CdwacOracle(sw, case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                        eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol,
+                                        fit_all=True, eps_qp=ks, quad_limit=True)
+    e_ref, it_ref, res = R.evgw(s, make, mode, max_iter=30, tol=1e-9)
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, prec="p64",
+                                quad_limit=True)
+    e, it, out = lib.cdwac_evgw(sysc, prm, mode, max_iter=30, tol=1e-9)
+    print(f"{mode}: {it} solves (oracle {it_ref}), core {e[0] * synth.HARTREE_EV:.6f} eV, Z {out[0]['z']:.3f}")
+    assert it < 30 and abs(it - it_ref) <= 1
+    np.testing.assert_allclose(e, e_ref, rtol=1e-8, atol=0)
+    assert out[0]["flags"] == 0 and 0.85 < out[0]["z"] <= 1.0
+
+
+@pytest.mark.parametrize("which", ["fp64_1core_nmo60", "ragged"])
+def test_hedin_with_quad_limit_fp64(lib, which):
+    """G_dH W0 with the analytic limit: dH_n and the roots against the oracle,
+    FP64 path, 1e-9 relative; Z in (0.85, 1] (the plain quadrature puts the
+    root on its step, with Z ~ 0.2)."""
+    case = cases.ragged() if which == "ragged" else cases.workload(which)
+    s = case.system
+    o = R.CdwacOracle(s, case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                      eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, fit_all=True, quad_limit=True)
+    run(lib, case, "p64", fit_all=True, quad_limit=True)
+    out, dh = lib.cdwac_qp_hedin(s.n_states)
+    for n in range(s.n_states):
+        r = o.solve_hedin(n)
+        print(f"{which} state {n}: G_dH W0 {out[n]['qp'] * synth.HARTREE_EV:.6f} eV "
+              f"(oracle {r[0] * synth.HARTREE_EV:.6f}), Z {out[n]['z']:.3f}")
+        assert abs(dh[n] - r[4]) <= 1e-9 * (abs(r[4]) + abs(o.sigma_x[n]))
+        assert out[n]["flags"] == r[3] == 0 and 0.85 < out[n]["z"] <= 1.0
+        assert abs(out[n]["qp"] - r[0]) <= 1e-9 * abs(r[0]), (n, out[n]["qp"], r[0])
+
+
+def test_full_cd_with_quad_limit_next_to_the_pole(lib):
+    """cdwac_sigma_cd with the analytic limit (W at i eta evaluated directly
+    for every m) next to the state's own pole: against the oracle's full CD
+    with the same limit, 1e-9 of |Sigma^x| + |Sigma|."""
+    case = cases.workload("fp64_1core_nmo60")
+    s = case.system
+    full = R.FullCdOracle(s, case.freq, case.weight, case.lo, case.hi, eta=case.eta, quad_limit=True)
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
+                                eta=case.eta, eta_ref=case.eta_ref, prec="p64", quad_limit=True)
+    for d in (-1e-3, -1e-5, 1e-5, 2e-2):
+        om = float(s.eps[0]) + d
+        got = lib.cdwac_sigma_cd(sysc, prm, 0, om)[0]
+        ref = full.sigma(0, om)
+        assert abs(got - ref) <= 1e-9 * (abs(ref) + abs(full.sigma_x[0])), (d, got, ref)
+
+
 def test_new_entry_points_reject_bad_arguments(lib):
     """Status codes of the batch, G-energy, evGW and full-CD entry points
     (checked before any launch)."""

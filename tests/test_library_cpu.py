@@ -27,16 +27,17 @@ def test_library_exports_every_header_symbol():
 def test_struct_layouts_match_header():
     # 4 int32, 1 pointer, 2 pointers, 2 pointers, 2 doubles
     assert ctypes.sizeof(cdwac.CdwacSystem) == 4 * 4 + 5 * 8 + 2 * 8
-    assert ctypes.sizeof(cdwac.CdwacStateOut) == 5 * 8 + 2 * 4
+    assert ctypes.sizeof(cdwac.CdwacStateOut) == 5 * 8 + 3 * 4 + 4      # tail padding to 8 bytes
 
 
 def test_params_layout_matches_header():
     # n_freq(+pad), freq, weight, n_ref_im(+pad), ref_im_idx, n_ref_re(+pad), ref_re, eta_ref, eta,
     # pade_tol, win_lo, win_hi, qp_tol, qp_maxit, prec, use_mlp_seed(+pad), mlp_accept, freq_rank_tol,
-    # fit_all, near_real_f64
-    assert ctypes.sizeof(cdwac.CdwacParams) == 8 + 16 + 8 + 8 + 8 + 8 + 3 * 8 + 2 * 8 + 8 + 3 * 4 + 4 + 2 * 8 + 8
-    assert cdwac.CdwacParams.fit_all.offset == ctypes.sizeof(cdwac.CdwacParams) - 8
-    assert cdwac.CdwacParams.near_real_f64.offset == ctypes.sizeof(cdwac.CdwacParams) - 4
+    # fit_all, near_real_f64, quad_limit (+pad)
+    assert ctypes.sizeof(cdwac.CdwacParams) == 8 + 16 + 8 + 8 + 8 + 8 + 3 * 8 + 2 * 8 + 8 + 3 * 4 + 4 + 2 * 8 + 16
+    assert cdwac.CdwacParams.fit_all.offset == ctypes.sizeof(cdwac.CdwacParams) - 16
+    assert cdwac.CdwacParams.near_real_f64.offset == ctypes.sizeof(cdwac.CdwacParams) - 12
+    assert cdwac.CdwacParams.quad_limit.offset == ctypes.sizeof(cdwac.CdwacParams) - 8
 
 
 def test_freq_decomposition_interpolates_w_family():
