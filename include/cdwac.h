@@ -73,7 +73,7 @@ typedef enum {
 enum {
     CDWAC_FLAG_NOROOT = 1,       /* no admissible root in the window: qp = NaN       */
     CDWAC_FLAG_FALLBACK = 2,     /* secant failed, scan + bisection was used          */
-    CDWAC_FLAG_MLP_ACCEPTED = 4  /* learned seed accepted without further iteration   */
+    CDWAC_FLAG_MLP_ACCEPTED = 4  /* learned seed, or one Newton step from it, accepted */
 };
 
 /* The molecule: mean-field energies and RI-V coefficients (Sec. 2.1-2.2). */
@@ -365,14 +365,21 @@ int cdwac_freq_decomposition(int32_t n_freq, const double *freq, double omega_lo
  * Ha (all four must lie in the window, else the plain search runs).  The
  * least-squares line through (d_j, f(w_j)) gives w_N = eps_n - mean(f) /
  * slope (eps_n - mean(f) if the slope is not positive), clamped to the
- * window.  Features (Ha): eps_n, eps_F, Sigma^x - v^xc, Re Sigma^c(w_0..w_3),
- * w_N - eps_n; the network predicts the correction w* - w_N.  Inputs are
+ * window.  Newton's method on the cubic interpolating the four values of f
+ * (divided differences), started from w_N, 40 steps or until the cubic's
+ * slope is not positive, gives w_C (w_N if that point is outside the window
+ * or not finite).  Features (Ha): eps_n, eps_F, Sigma^x - v^xc,
+ * Re Sigma^c(w_0..w_3), w_C - eps_n; the network predicts w* - w_C.  Inputs are
  * standardised with (mu, sd) and the output is y * out_sd + out_mu.  A
  * second pass evaluates f at the seed and at seed +- 1e-4 Ha: the seed is
  * the root if |f| <= mlp_accept and its Z is in (0, 1] (flag
- * CDWAC_FLAG_MLP_ACCEPTED, two passes in all); otherwise the secant continues
- * from the sample nearest the seed and the seed, and if that search fails
- * the plain one from eps_n runs. */
+ * CDWAC_FLAG_MLP_ACCEPTED, two passes in all).  Otherwise, if that Z is in
+ * (0, 1], a third pass evaluates f at the Newton step w_1 = seed - f Z and at
+ * w_1 +- 1e-4 Ha, and w_1 is the root under the same test (the same flag,
+ * three passes); if it fails the secant continues from the seed and w_1.
+ * With an unphysical Z at the seed the secant continues from the sample
+ * nearest the seed and the seed.  If that secant has not converged after 12
+ * steps (or qp_maxit, if smaller) the plain search from eps_n runs.  An accepted root is good to mlp_accept in f, not to qp_tol. */
 #define CDWAC_MLP_NIN 8
 #define CDWAC_MLP_NPARAM 4801
 

@@ -20,6 +20,11 @@ namespace cdwac {
 constexpr double kScanStep = 0.01, kScanFmax = 0.1, kBisectTol = 1e-12, kZStep = 1e-4, kFTol = 1e-9,
                  kRootFTol = 1e-8;
 constexpr int kQpThreads = 256, kMaxFreq = 512;
+// Secant steps allowed after a rejected learned seed before the plain search
+// from eps_n takes over (a seed in the wrong basin must not cost qp_maxit).
+constexpr int kSeedSecantIt = 12;
+// Newton iterations on the seed samples' interpolating cubic.
+constexpr int kCubicIt = 40;
 // Offsets from eps_n (Ha) of the learned seed's four self-energy samples
 // (symmetric: they sum to zero).
 __constant__ const double kSeedOffset[4] = {-0.1, -0.05, 0.05, 0.1};
@@ -189,6 +194,30 @@ __device__ float mlp_one(const float* __restrict__ th, const float* x, Shared& s
 
 // Root of the QP equation for state s of the system A, written to *dst by
 // thread 0 (the whole workgroup evaluates Sigma together).
+// Zero of the cubic interpolating (d_j, f_j), j = 0..3, in Newton's divided-
+// difference form, by Newton's method on the cubic started from the line
+// estimate wl (absolute energies: d = w - e_n).  An iteration stops where the
+// cubic's slope is not positive; a result outside [lo, hi] or not finite
+// gives wl back.
+__device__ inline double cubic_root(const double* d, const double* f, double e_n, double wl, double lo,
+                                    double hi) {
+    double a[4] = {f[0], f[1], f[2], f[3]};
+    for (int k = 1; k < 4; ++k)
+        for (int j = 3; j >= k; --j) a[j] = (a[j] - a[j - 1]) / (d[j] - d[j - k]);
+    double x = wl - e_n;
+    for (int it = 0; it < kCubicIt; ++it) {
+        double p = a[3], dp = 0.0;
+        for (int k = 2; k >= 0; --k) {
+            dp = dp * (x - d[k]) + p;
+            p = p * (x - d[k]) + a[k];
+        }
+        if (!(dp > 0.0)) break;
+        x -= p / dp;
+    }
+    const double w = e_n + x;
+    return (isfinite(w) && lo <= w && w <= hi) ? w : wl;
+}
+
 __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
     for (int k = threadIdx.x; k < A.n_freq; k += kQpThreads) {
         sh.freq[k] = A.freq[k];
@@ -229,9 +258,9 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
     bool done = false;
     // secant iteration from the pair (xa, fa), (xb, fb); on convergence with a
     // physical Z factor the root and Z are taken
-    auto secant = [&](double xa, double fa, double xb, double fb) {
+    auto secant = [&](double xa, double fa, double xb, double fb, int maxit) {
         bool ok = false;
-        for (int it = 0; it < A.qp_maxit; ++it) {
+        for (int it = 0; it < maxit; ++it) {
             if (fb == fa) break;
             const double xc = xb - fb * (xb - xa) / (fb - fa);
             if (!(lo <= xc && xc <= hi)) break;
@@ -253,11 +282,13 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
     };
     if (A.use_mlp && lo <= e_n + kSeedOffset[0] && e_n + kSeedOffset[3] <= hi) {
         // learned seed: round 1 evaluates Sigma^c at four fixed offsets from
-        // eps_n; the straight line fitted through f there gives a Newton-like
-        // estimate w_N, and the network predicts the remaining correction
-        // w* - w_N from eps_n, eps_F, Sigma^x - v^xc, the four Sigma^c values
-        // and w_N - eps_n.  Round 2 evaluates f at the seed and at seed +- h:
-        // the seed is the root if |f| <= mlp_accept and Z is in (0, 1].
+        // eps_n; the zero w_C of the cubic through the four values of f is
+        // the base estimate, and the network predicts the remaining
+        // correction w* - w_C from eps_n, eps_F, Sigma^x - v^xc, the four
+        // Sigma^c values and w_C - eps_n.  Round 2 evaluates f at the seed and at seed +- h:
+        // the seed is the root if |f| <= mlp_accept and Z is in (0, 1].  Else,
+        // with a physical Z, round 3 takes one Newton step with that slope and
+        // applies the same test to its point.
         double xs[4], fs[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) xs[j] = e_n + kSeedOffset[j];
@@ -272,30 +303,47 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
         const double slope = sdf / sdd, mean = 0.25 * sf;      // the offsets sum to zero
         double wn = slope > 0.0 ? e_n - mean / slope : e_n - mean;
         wn = fmin(fmax(wn, lo), hi);
-        double raw[8] = {e_n, A.eps_f, sx - vxc, 0.0, 0.0, 0.0, 0.0, wn - e_n};
+        const double wc = cubic_root(kSeedOffset, fs, e_n, wn, lo, hi);
+        double raw[8] = {e_n, A.eps_f, sx - vxc, 0.0, 0.0, 0.0, 0.0, wc - e_n};
 #pragma unroll
         for (int j = 0; j < 4; ++j) raw[3 + j] = xs[j] - e_n + vxc - fs[j] - sx;   // Sigma^c(x_j)
         float feat[8];
         for (int i = 0; i < 8; ++i) feat[i] = (float)((raw[i] - A.mlp_mu[i]) / A.mlp_sd[i]);
         const float y = mlp_one(A.mlp_theta, feat, sh);
-        const double seed = wn + (double)y * A.mlp_out_sd + A.mlp_out_mu;
+        const double seed = wc + (double)y * A.mlp_out_sd + A.mlp_out_mu;
         if (seed - kZStep >= lo && seed + kZStep <= hi) {
             const double ps[3] = {seed, seed + kZStep, seed - kZStep};
             double pf[3];
             f_multi(ps, pf);
             const double z = 2.0 * kZStep / (pf[1] - pf[2]);
-            if (fabs(pf[0]) <= A.mlp_accept && 0.0 < z && z <= 1.0) {
+            const bool phys = 0.0 < z && z <= 1.0;
+            if (fabs(pf[0]) <= A.mlp_accept && phys) {
                 root = seed;
                 zf = z;
                 flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
                 done = true;
+            } else if (phys && seed - pf[0] * z - kZStep >= lo && seed - pf[0] * z + kZStep <= hi) {
+                // Newton step from the seed (f' = 1 / Z)
+                const double x1 = seed - pf[0] * z;
+                const double qs[3] = {x1, x1 + kZStep, x1 - kZStep};
+                double qf[3];
+                f_multi(qs, qf);
+                const double z1 = 2.0 * kZStep / (qf[1] - qf[2]);
+                if (fabs(qf[0]) <= A.mlp_accept && 0.0 < z1 && z1 <= 1.0) {
+                    root = x1;
+                    zf = z1;
+                    flags |= CDWAC_FLAG_MLP_ACCEPTED_DEV;
+                    done = true;
+                } else {
+                    done = secant(seed, pf[0], x1, qf[0], min(A.qp_maxit, kSeedSecantIt));
+                }
             } else {
                 // the secant continues from the sample nearest the seed and the seed
                 int jn = 0;
 #pragma unroll
                 for (int j = 1; j < 4; ++j)
                     if (fabs(xs[j] - seed) < fabs(xs[jn] - seed)) jn = j;
-                done = secant(xs[jn], fs[jn], seed, pf[0]);
+                done = secant(xs[jn], fs[jn], seed, pf[0], min(A.qp_maxit, kSeedSecantIt));
             }
         }
     }
@@ -303,7 +351,7 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
     // (also where a seeded search failed)
     if (!done) {
         const double w0 = e_n, f0 = f(w0), w1 = w0 - f0;
-        if (lo <= w1 && w1 <= hi) done = secant(w0, f0, w1, f(w1));
+        if (lo <= w1 && w1 <= hi) done = secant(w0, f0, w1, f(w1), A.qp_maxit);
     }
     if (!done) {
         flags |= CDWAC_FLAG_FALLBACK_DEV;

@@ -154,13 +154,13 @@ def test_seed_on_an_unphysical_crossing_falls_back(lib):
     xb = float(xs[bad[np.argmax(viol)]])
     print(f"{len(bad)} grid points with |f| < 0.11 Ha and Z outside (0, 1]; seed at Z = "
           f"{z[bad[np.argmax(viol)]]:.4f}, f = {f[bad[np.argmax(viol)]]:.4f} Ha")
-    # w_N: the line estimate of the seed's four samples (the network adds
+    # w_C: the base estimate of the seed's four samples (the network adds
     # out_mu to it when every weight is zero)
-    d = np.array([-0.1, -0.05, 0.05, 0.1])
-    fs = (e_n + d) - e_n - lib.cdwac_sigma((e_n + d)[None, :])[0] + vxc
-    slope, mean = float(np.dot(d, fs) / np.dot(d, d)), float(fs.mean())
-    wn = min(max(e_n - mean / slope if slope > 0.0 else e_n - mean, case.lo[0]), case.hi[0])
-    lib.cdwac_mlp_set_model(np.zeros(cd().MLP_NPARAM), np.zeros(8), np.ones(8), xb - wn, 1.0)
+    from paper_2305_15955_amd import seed_train
+    en, vx, lo, hi = np.array([e_n]), np.array([vxc]), case.lo[:1], case.hi[:1]
+    sig4 = seed_train.samples(lib, en)
+    wc = float(seed_train.cubic_estimate(en, vx, sig4, lo, hi, seed_train.line_estimate(en, vx, sig4, lo, hi))[0])
+    lib.cdwac_mlp_set_model(np.zeros(cd().MLP_NPARAM), np.zeros(8), np.ones(8), xb - wc, 1.0)
     prm, arrs = params(lib, case, prec="p64", use_mlp_seed=True, mlp_accept=0.12)
     got = lib.cdwac_solve(sysc, prm)[0]
     print(f"seed at {xb:.6f} Ha; plain root {plain['qp']:.12f}, seeded search {got['qp']:.12f}, "

@@ -217,7 +217,7 @@ def test_deploy_naux6600_learned_seed(lib):
     (0.5, 1] and |f| <= 1e-8 Ha, or <= 1 meV where the seed is accepted (the
     secant is the fallback and decides); all states within 1 meV of the
     reference; an accepted seed ends the search after 2 passes over the
-    tables.  Sampled Pi entries against the oracle's one-by-one definition."""
+    tables (3 where the Newton step from it is accepted).  Sampled Pi entries against the oracle's one-by-one definition."""
     import torch
     case = cases.workload("mlp_deploy_naux6600")
     s = case.system
@@ -262,4 +262,4 @@ def test_deploy_naux6600_learned_seed(lib):
     print(f"seed accepted for {n_acc} of {s.n_states}; mean passes {mean_plain:.2f} -> {mean_seeded:.2f}")
     for o1 in res["seeded"]:
         if o1["flags"] & R.FLAG_MLP_ACCEPTED:
-            assert o1["n_rounds"] == 2
+            assert o1["n_rounds"] in (2, 3)
