@@ -145,7 +145,8 @@ typedef struct {
                                   the evGW0 and G_dH W0 roots sit at such a point for the
                                   state's own m.  Applies to the orbitals with a model (the
                                   fit range, or every m with fit_all).  0: the plain
-                                  quadrature.  Not supported by cdwac_solve_batch.       */
+                                  quadrature.  May differ between the systems of a
+                                  batch.                                                   */
 } cdwac_params;
 
 /* Result for one state (host, written by cdwac_qp / cdwac_solve). */

@@ -1210,8 +1210,6 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
         TRY(validate_params(ctx, &sys[j], &prm[j]));
         if (prm[j].use_mlp_seed && !ctx->have_mlp)
             return fail(ctx, CDWAC_EINVAL, "system %d: use_mlp_seed set but no model installed", j);
-        if (prm[j].quad_limit)
-            return fail(ctx, CDWAC_EINVAL, "system %d: quad_limit is not supported in a batch", j);
         const int m = prm[j].n_ref_im + prm[j].n_ref_re;
         if (j == 0) n_pts = m;
         if (m != n_pts || prm[j].pade_tol != prm[0].pade_tol)
@@ -1248,6 +1246,7 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
     const size_t o_u = bump(total, fits), o_w = bump(total, fits), o_coef = bump(total, fits),
                  o_node = bump(total, fits);
     const size_t o_nterm = bump(total, sizeof(int) * std::max(f_tot, 1));
+    const size_t o_w0 = bump(total, sizeof(double) * std::max(f_tot, 1));
     const size_t o_args = bump(total, sizeof(QpArgs) * n_sys);
     const size_t o_map = bump(total, sizeof(int2) * s_tot);
     const size_t o_out = bump(total, sizeof(QpOut) * s_tot);
@@ -1299,6 +1298,7 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
         a.vxc = (const double*)(base + b.vxc);
         a.win_lo = (const double*)(base + b.win_lo);
         a.win_hi = (const double*)(base + b.win_hi);
+        a.w0 = prm[j].quad_limit ? (const double*)(base + o_w0) + fit0 : nullptr;
         b.args = a;
         b.fit0 = fit0;
         fit0 += n_fit[j];
@@ -1314,6 +1314,15 @@ int cdwac_solve_batch(cdwac_ctx* ctx, int32_t n_sys, const cdwac_system* sys, co
     launch_thiele_fit(st, f_tot, n_pts, (const double*)(base + o_u), (const double*)(base + o_w), prm[0].pade_tol,
                       (double*)(base + o_coef), (double*)(base + o_node), (int*)(base + o_nterm));
     LAUNCHCK();
+    // W at a_m = 0 for the systems with the analytic limit of I_n (each its own eta)
+    for (int j = 0; j < n_sys; ++j) {
+        if (!prm[j].quad_limit || n_fit[j] == 0) continue;
+        const size_t fo = (size_t)bs[j].fit0 * n_pts * 2;
+        launch_w0_from_fits(st, n_fit[j], n_pts, (const double*)(base + o_coef) + fo,
+                            (const double*)(base + o_node) + fo, (const int*)(base + o_nterm) + bs[j].fit0,
+                            prm[j].eta, (double*)(base + o_w0) + bs[j].fit0);
+        LAUNCHCK();
+    }
     TRY(seg_end(ctx));
     // (a6)-(a8) the QP roots of every state in one launch
     std::vector<QpArgs> args(n_sys);

@@ -56,7 +56,7 @@ def one_transition():
     return build(s, 32, 4, 4, 30.0, name="one_transition")
 
 
-def oracle(case):
+def oracle(case, **kw):
     from oracle import cdwac_ref as R
     return R.CdwacOracle(case.system, case.freq, case.weight, case.ref_im, case.ref_re, case.lo,
-                         case.hi, eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol)
+                         case.hi, eta=case.eta, eta_ref=case.eta_ref, pade_tol=case.pade_tol, **kw)

@@ -102,14 +102,29 @@ def test_batch_rejects_mixed_pade_sizes(lib):
     assert e.value.code == cdwac.CDWAC_EINVAL
 
 
-def test_batch_rejects_quad_limit(lib):
-    from paper_2305_15955_amd import cdwac
-    specs = [dict(n_mo=40, n_occ=7, n_aux=132, n_core=2, sigma=0.03, seed=1)]
+def test_small_batch_fp64_quad_limit(lib):
+    """The analytic a_m -> 0 limit in a batch, switched on for every other
+    system: each system bit-identical to its own cdwac_solve with the same
+    parameters, and the limit's systems within 1e-9 of the oracle with the
+    limit."""
+    specs = [dict(n_mo=n, n_occ=max(2, round(n / 6)), n_aux=round(3.3 * n), n_core=c,
+                  sigma=math.sqrt(synth.SCREENING / (round(n / 6) * (n - round(n / 6)))), seed=700 + j)
+             for j, (n, c) in enumerate(((40, 2), (75, 1), (52, 4), (90, 3), (61, 2)))]
     cs = batch_cases(specs, n_freq=32)
-    systems, params, keep = descriptors(lib, cs, "p64", quad_limit=True)
-    with pytest.raises(cdwac.CdwacError) as e:
-        lib.cdwac_solve_batch(systems, params)
-    assert e.value.code == cdwac.CDWAC_EINVAL
+    systems, params, keep = [], [], []
+    for j, c in enumerate(cs):
+        sy, pr, kp = descriptors(lib, [c], "p64", fit_all=True, quad_limit=(j % 2 == 0))
+        systems += sy
+        params += pr
+        keep += kp
+    res = lib.cdwac_solve_batch(systems, params)
+    for j, c in enumerate(cs):
+        assert same_result(res[j], lib.cdwac_solve(systems[j], params[j])), j
+        if j % 2 == 0:
+            for n, r in enumerate(cases.oracle(c, fit_all=True, quad_limit=True).solve_all()):
+                assert res[j][n]["flags"] == r[3], (j, n)
+                if not r[3] & R.FLAG_NOROOT:
+                    assert abs(res[j][n]["qp"] - r[0]) <= 1e-9 * abs(r[0]), (j, n, res[j][n]["qp"], r[0])
 
 
 def test_uneven_batch_48_systems(lib):
@@ -170,6 +185,21 @@ def test_uneven_batch_48_systems(lib):
               flush=True)
     for j in (order[0], order[-1]):
         assert same_result(res[j], lib.cdwac_solve(systems[j], params[j])), j
+    # with the analytic limit of the integral term (quad_limit) the step at the
+    # other cores' levels is gone: system 37 again, in a batch with the two
+    # smallest systems, has a root for every state, within 1 meV of the
+    # oracle with the same limit
+    sub = [37, int(order[0]), int(order[1])]
+    sy, pr, kp = descriptors(lib, [cs[j] for j in sub], "f16x3", fit_all=True, near_real_f64=True, quad_limit=True)
+    res_l = lib.cdwac_solve_batch(sy, pr)
+    o37 = cases.oracle(cs[37], fit_all=True, quad_limit=True)
+    for n, x in enumerate(res_l[0]):
+        r = o37.solve(n)
+        print(f"system 37 state {n} with the limit: {x['qp'] * synth.HARTREE_EV:.4f} eV, Z {x['z']:.3f}, "
+              f"{abs(x['qp'] - r[0]) / MEV:.4f} meV from the oracle", flush=True)
+        assert not x["flags"] & R.FLAG_NOROOT and r[3] == 0 and 0.9 < x["z"] <= 1.0, (n, x, r)
+        assert abs(x["qp"] - r[0]) <= MEV, (n, x["qp"], r[0])
+    del sy, pr, kp
     for j in order[:5]:
         o = cases.oracle(cs[j])
         for n, r in enumerate(o.solve_all()):
