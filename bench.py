@@ -199,7 +199,8 @@ def scaling(sizes, cd_qp_max):
     every residue of one omega; its cost per QP solve is the imaginary-axis
     part once plus the residue part per self-energy evaluation (as many as the
     CD-WAC solve used).  Up to N_mo = cd_qp_max the full-CD QP energy is also
-    solved on the GPU (secant over cdwac_sigma_cd) to give CD-WAC's error."""
+    solved on the GPU (secant over cdwac_sigma_cd, each evaluation computing
+    the imaginary-axis part again), timed, to give CD-WAC's error."""
     import torch
     from paper_2305_15955_amd import cdwac, grids, synth
     lib = cdwac.Cdwac(0)
@@ -237,7 +238,14 @@ def scaling(sizes, cd_qp_max):
         row["cd_over_cdwac"] = row["cd_qp_estimate_s"] / t_wac
         if n_mo <= cd_qp_max:
             e_n = float(s.eps[0])
-            f = lambda w: w - e_n - lib.cdwac_sigma_cd(sysc, prm, 0, w)[0] + float(out["sigma_x"])
+            n_cd = [0]
+
+            def f(w):
+                n_cd[0] += 1
+                v = w - e_n - lib.cdwac_sigma_cd(sysc, prm, 0, w)[0] + float(out["sigma_x"])
+                log(f"  N_mo={n_mo} full-CD evaluation {n_cd[0]}: f = {v:.3e} Ha")
+                return v
+            t = time.perf_counter()
             w0, f0 = e_n, f(e_n)
             w1 = w0 - f0
             f1 = f(w1)
@@ -247,6 +255,8 @@ def scaling(sizes, cd_qp_max):
                 f1 = f(w1)
                 if abs(w1 - w0) < 1e-10:
                     break
+            row["cd_qp_solve_s"] = time.perf_counter() - t
+            row["cd_qp_solve_evals"] = n_cd[0]
             row["cd_qp_ev"] = w1 * synth.HARTREE_EV
             row["cdwac_minus_cd_mev"] = (qp - w1) * synth.HARTREE_EV * 1e3
         log(f"scaling N_mo={n_mo}: CD-WAC {t_wac:.3f} s, CD residue part {t_res:.3f} s x {out['n_evals']} "
@@ -260,9 +270,11 @@ def scaling(sizes, cd_qp_max):
         x = np.log([r["n_mo"] for r in big])
         y = np.log([r[key] for r in big])
         return float(np.polyfit(x, y, 1)[0])
+    solved = all("cd_qp_solve_s" in r for r in rows[-3:])
     return {"metric": "full CD vs CD-WAC cost per core QP energy on one GPU (FP64 path)",
             "unit": "s", "rows": rows,
             "exponent_cdwac": slope("cdwac_s"), "exponent_cd": slope("cd_qp_estimate_s"),
+            "exponent_cd_solved": slope("cd_qp_solve_s") if solved else None,
             "exponent_cd_per_eval": slope("cd_residue_part_s"),
             "data": "synthetic (seeded Gaussian RI coefficients, no molecule)"}
 
@@ -350,7 +362,7 @@ def main():
                     help="instead of the benchmark: CD-WAC against full CD over (N_core, N_valence) (one JSON line)")
     args = ap.parse_args()
     if args.scaling:
-        print(json.dumps(scaling([60, 120, 240, 480, 960], 240)), flush=True)
+        print(json.dumps(scaling([60, 120, 240, 480, 960], 960)), flush=True)
         return
     if args.literal_screening:
         print(json.dumps(literal_screening()), flush=True)
