@@ -244,6 +244,38 @@ def test_near_real_planes_on_the_fp64_path(lib, prec):
         assert abs(out[n]["qp"] - r[0]) <= MEV, (n, out[n]["qp"], r[0])
 
 
+# largest W error against the FP64 path, relative to the state's largest W,
+# on the imaginary nodes and at the near-real points: (imaginary, near-real);
+# measured on the ragged case: f16x3 (6.1e-8, 9.2e-5), b16x3 (1.0e-6, 2.3e-4),
+# f16 (1.5e-5, 8.5e-3)
+W16_BOUND = {"f16x3": (3e-7, 3e-4), "b16x3": (5e-6, 1e-3), "f16": (5e-5, 3e-2)}
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "b16x3", "f16"])
+def test_w_error_of_the_16bit_modes(lib, prec):
+    """How far each 16-bit mode's W tables are from the FP64 path's on the
+    ragged case (every imaginary node contracted): the imaginary-axis W
+    carries the contraction's rounding; at the near-real points, within
+    eta_ref of RPA poles, a relative error d of Pi moves each pole by
+    ~d * Omega / eta_ref of its width, so the error there is larger.  Bounds
+    per mode in W16_BOUND (measured values printed)."""
+    case = cases.ragged()
+    s = case.system
+    run(lib, case, "p64")
+    wi64, wr64, _, (m0, m1) = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+    run(lib, case, prec)
+    wi, wr, _, _ = lib.cdwac_w_table(s.n_states, s.n_mo, len(case.freq), len(case.ref_re))
+    e_im, e_re, f = 0.0, 0.0, 0
+    for n in range(s.n_states):
+        e_im = max(e_im, np.max(np.abs(wi[n] - wi64[n])) / np.max(np.abs(wi64[n])))
+        nf = m1[n] - m0[n]
+        e_re = max(e_re, np.max(np.abs(wr[f:f + nf] - wr64[f:f + nf])) / np.max(np.abs(wr64[f:f + nf])))
+        f += nf
+    print(f"{prec}: W error / max|W|: imaginary nodes {e_im:.2e}, near-real points {e_re:.2e}")
+    b_im, b_re = W16_BOUND[prec]
+    assert e_im <= b_im and e_re <= b_re, (prec, e_im, e_re)
+
+
 def test_default_setting_reduced_precision(lib):
     """CD-WAC(20, 20, 200) with Pi in one fp16 product, W in the fp16 split and
     skeleton imaginary nodes: within 1 meV of the oracle."""
