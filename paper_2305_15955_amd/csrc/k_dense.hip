@@ -19,68 +19,82 @@
 namespace cdwac {
 
 // ============================================================================
-// FP64 MFMA tile machinery: 64 x 64 output tile, 4 waves of 32 x 32,
-// K chunks of 16 staged in LDS as [k][row].
+// FP64 MFMA tile machinery: 128 x 128 output tile, 4 waves of 64 x 64 (4 x 4
+// blocks of v_mfma_f64_16x16x4), K chunks of 16 staged in LDS as [k][row],
+// double-buffered.  Per chunk a workgroup stages 32 KiB for 1024 matrix-core
+// blocks (a 64 x 64 tile needs twice the bytes per flop, and ran 1.27x slower
+// on the polarizability); two workgroups per CU.
 // ============================================================================
 
-constexpr int F_BT = 64, F_KC = 16, F_LD = F_BT + 2;
+constexpr int F_BT = 128, F_KC = 16, F_LD = F_BT + 2;
 
 struct F64Stage {
     double a[F_KC][F_LD];
     double b[F_KC][F_LD];
 };
 
-// acc[bi][bj] += A_tile * B_tile^T for one staged chunk.
-__device__ inline void f64_chunk(const F64Stage& st, int wr, int wc, int lane, v4d (&acc)[2][2]) {
+__device__ inline void f64_chunk(const F64Stage& st, int wr, int wc, int lane, v4d (&acc)[4][4]) {
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < F_KC / 4; ++kk) {
         const int k = kk * 4 + lk;
-        double a0 = st.a[k][wr * 32 + lr], a1 = st.a[k][wr * 32 + 16 + lr];
-        double b0 = st.b[k][wc * 32 + lr], b1 = st.b[k][wc * 32 + 16 + lr];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a[i] = st.a[k][wr * 64 + i * 16 + lr];
+            b[i] = st.b[k][wc * 64 + i * 16 + lr];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
 }
 
-// Thread t loads row t/4, k = (t%4)*4 .. +3 of a 64 x 16 chunk.
+// Thread t loads row t/2, k = (t%2)*8 .. +7 of a 128 x 16 chunk of A and of B
+// (B scaled by cw when given).
 struct F64Frag {
-    double a[4], b[4];
+    double a[8], b[8];
 };
 
-__device__ inline void f64_load(F64Frag& fr, const double* __restrict__ arow,
-                                const double* __restrict__ brow, const double* __restrict__ cw,
-                                int64_t k0) {
+__device__ inline void f64_load(F64Frag& fr, const double* __restrict__ arow, const double* __restrict__ brow,
+                                 const double* __restrict__ cw, int64_t k0) {
     const double2* pa = reinterpret_cast<const double2*>(arow + k0);
     const double2* pb = reinterpret_cast<const double2*>(brow + k0);
-    double2 a01 = pa[0], a23 = pa[1], b01 = pb[0], b23 = pb[1];
-    fr.a[0] = a01.x; fr.a[1] = a01.y; fr.a[2] = a23.x; fr.a[3] = a23.y;
-    fr.b[0] = b01.x; fr.b[1] = b01.y; fr.b[2] = b23.x; fr.b[3] = b23.y;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double2 x = pa[e], y = pb[e];
+        fr.a[2 * e] = x.x;
+        fr.a[2 * e + 1] = x.y;
+        fr.b[2 * e] = y.x;
+        fr.b[2 * e + 1] = y.y;
+    }
     if (cw) {
         const double2* pc = reinterpret_cast<const double2*>(cw + k0);
-        double2 c01 = pc[0], c23 = pc[1];
-        fr.b[0] *= c01.x; fr.b[1] *= c01.y; fr.b[2] *= c23.x; fr.b[3] *= c23.y;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double2 c = pc[e];
+            fr.b[2 * e] *= c.x;
+            fr.b[2 * e + 1] *= c.y;
+        }
     }
 }
 
 __device__ inline void f64_store(F64Stage& st, const F64Frag& fr, int row, int kq) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < 8; ++e) {
         st.a[kq + e][row] = fr.a[e];
         st.b[kq + e][row] = fr.b[e];
     }
 }
 
-// Full K loop: acc = A[rows a0..a0+63] * (B[rows b0..b0+63] * diag(cw))^T.
-__device__ inline void f64_tile_product(const double* __restrict__ A, int64_t lda,
-                                        const double* __restrict__ B, int64_t ldb,
-                                        const double* __restrict__ cw, int64_t K,
-                                        F64Stage (&st)[2], v4d (&acc)[2][2]) {
+// acc = A[128 rows] * (B[128 rows] * diag(cw))^T over K (a multiple of 16).
+__device__ inline void f64_tile_product(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                         int64_t ldb, const double* __restrict__ cw, int64_t K,
+                                         F64Stage (&st)[2], v4d (&acc)[4][4]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
-    const int row = t >> 2, kq = (t & 3) * 4;
+    const int row = t >> 1, kq = (t & 1) * 8;
     const double* arow = A + (int64_t)row * lda + kq;
     const double* brow = B + (int64_t)row * ldb + kq;
     const double* crow = cw ? cw + kq : nullptr;
@@ -106,8 +120,9 @@ __device__ inline void lower_tile(int t, int& I, int& J) {
     J = t - i * (i + 1) / 2;
 }
 
-// eps_f = delta_f I - X diag(c_f) X^T on the lower 64 x 64 tiles, FP64.
-__global__ __launch_bounds__(256) void k_pi_f64(const double* __restrict__ x, int64_t kpad,
+// eps_f = delta_f I - X diag(c_f) X^T on the lower 128 x 128 tiles, FP64
+// (npad a multiple of 128, kpad of 16).
+__global__ __launch_bounds__(256, 2) void k_pi_f64(const double* __restrict__ x, int64_t kpad,
                                                 const double* __restrict__ cw,
                                                 const int* __restrict__ idflag,
                                                 double* __restrict__ E, int npad, int n_f) {
@@ -117,28 +132,29 @@ __global__ __launch_bounds__(256) void k_pi_f64(const double* __restrict__ x, in
     const int f = bid / T;
     int I, J;
     lower_tile(bid % T, I, J);
-    v4d acc[2][2] = {};
+    v4d acc[4][4] = {};
     f64_tile_product(x + (int64_t)I * F_BT * kpad, kpad, x + (int64_t)J * F_BT * kpad, kpad,
-                     cw + (int64_t)f * kpad, kpad, st, acc);
+                      cw + (int64_t)f * kpad, kpad, st, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
     const double id = idflag[f] ? 1.0 : 0.0;
     double* Ef = E + (int64_t)f * npad * npad;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int P = I * F_BT + wr * 32 + bi * 16 + (lane >> 4) + 4 * r;
-                int Q = J * F_BT + wc * 32 + bj * 16 + (lane & 15);
+                int P = I * F_BT + wr * 64 + bi * 16 + (lane >> 4) + 4 * r;
+                int Q = J * F_BT + wc * 64 + bj * 16 + (lane & 15);
                 Ef[(int64_t)P * npad + Q] = (P == Q ? id : 0.0) - acc[bi][bj][r];
             }
 }
 
-// partial[f][I][c] = sum_{P in tile I} B[c][P] (Lambda_f B^T)[P][c], FP64.
-__global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, int npad,
-                                               const double* __restrict__ bt, int cpad,
-                                               int f0, double* __restrict__ partial) {
+// partial[f][I][c] = sum_{P in tile I} B[c][P] (Lambda_f B^T)[P][c], FP64,
+// 128 x 128 tiles (npad and cpad multiples of 128).
+__global__ __launch_bounds__(256, 2) void k_w_f64(const double* __restrict__ lam, int npad,
+                                                  const double* __restrict__ bt, int cpad,
+                                                  int f0, double* __restrict__ partial) {
     __shared__ F64Stage st[2];
     __shared__ double red[2][F_BT];
     const int ni = npad / F_BT, nc = cpad / F_BT;
@@ -147,24 +163,24 @@ __global__ __launch_bounds__(256) void k_w_f64(const double* __restrict__ lam, i
     const int rem = bid % (ni * nc);
     const int I = rem % ni, J = rem / ni;
     const double* L = lam + (int64_t)(f0 + fl) * npad * npad;
-    v4d acc[2][2] = {};
+    v4d acc[4][4] = {};
     f64_tile_product(L + (int64_t)I * F_BT * npad, npad, bt + (int64_t)J * F_BT * npad, npad,
-                     nullptr, npad, st, acc);
+                      nullptr, npad, st, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-        const int c = J * F_BT + wc * 32 + bj * 16 + (lane & 15);
+    for (int bj = 0; bj < 4; ++bj) {
+        const int c = J * F_BT + wc * 64 + bj * 16 + (lane & 15);
         double s = 0.0;
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int P = I * F_BT + wr * 32 + bi * 16 + (lane >> 4) + 4 * r;
+                int P = I * F_BT + wr * 64 + bi * 16 + (lane >> 4) + 4 * r;
                 s += bt[(int64_t)c * npad + P] * acc[bi][bj][r];
             }
         s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
-        if (lane < 16) red[wr][wc * 32 + bj * 16 + lane] = s;
+        if (lane < 16) red[wr][wc * 64 + bj * 16 + lane] = s;
     }
     __syncthreads();
     if (threadIdx.x < F_BT) {
