@@ -469,7 +469,7 @@ def main():
         # no single-kernel roofline
         res["roofline"] = None
     res["stages_ms"] = stages
-    # spectral function (Sec. 4) on 5000 points per state over a 50 eV range,
+    # spectral function (Sec. 5.5) on 5000 points per state over a 50 eV range,
     # from the prepared tables of the last step
     om = np.stack([s.eps[s.state_idx[n]] + np.linspace(-25.0, 25.0, 5000) / synth.HARTREE_EV
                    for n in range(s.n_states)])
@@ -483,6 +483,16 @@ def main():
     res["n_evals_mean"] = float(np.mean([o["n_evals"] for o in out]))
     res["n_rounds_mean"] = float(np.mean([o["n_rounds"] for o in out]))
     res["seed_accepted"] = int(sum(bool(o["flags"] & cdwac.FLAG_MLP_ACCEPTED) for o in out))
+    # per-state error against the oracle's QP energies where they are stored
+    # for this workload (tests/golden, written by the oracle alone)
+    stored = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.json")
+    res["mev_err_vs_oracle"] = None
+    if os.path.exists(stored):
+        g = json.load(open(stored))
+        if g.get("workload") == args.workload and len(g["qp"]) == len(out):
+            e = [abs(o["qp"] - q) * synth.HARTREE_EV * 1e3 for o, q in zip(out, g["qp"])]
+            res["mev_err_vs_oracle"] = {"max": max(e), "mean": float(np.mean(e)), "per_state": e,
+                                        "stored": os.path.relpath(stored, ROOT)}
 
     res["inversion_residual"] = lib.cdwac_inversion_residual()[0]
 

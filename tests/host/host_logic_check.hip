@@ -154,6 +154,13 @@ int main() {
         Case g(s, rng);
         g.prm.n_ref_re = 300;
         expect(validate_params(nullptr, &g.sys, &g.prm) == CDWAC_EINVAL, "too many references");
+        Case g2(s, rng);
+        g2.prm.n_ref_re = kMaxPade + 1 - g2.prm.n_ref_im;
+        expect(g2.prm.n_ref_re < 0 || validate_params(nullptr, &g2.sys, &g2.prm) == CDWAC_EINVAL,
+               "one reference point beyond the limit");
+        Case g3(s, rng);
+        g3.prm.n_freq = qp_max_freq() + 1;
+        expect(validate_params(nullptr, &g3.sys, &g3.prm) == CDWAC_EINVAL, "one imaginary node beyond the limit");
         Case h(s, rng);
         h.state_idx[0] = s.n_mo;
         expect(validate_system(nullptr, &h.sys) == CDWAC_EINVAL, "state index out of range");

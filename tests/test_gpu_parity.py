@@ -484,6 +484,30 @@ def test_full_cd_with_quad_limit_next_to_the_pole(lib):
         assert abs(got - ref) <= 1e-9 * (abs(ref) + abs(full.sigma_x[0])), (d, got, ref)
 
 
+def test_maximum_grid_and_reference_sizes(lib):
+    """The largest imaginary grid (512 Gauss-Legendre nodes, the QP kernel's
+    shared-memory table) and the largest reference set (M = 256: 128
+    imaginary and 128 near-real points, four per lane in the fit kernel) on
+    the 60-orbital case, FP64 path: QP energy and Sigma at three points
+    against the oracle, 1e-9 relative."""
+    base = cases.workload("fp64_1core_nmo60")
+    case = cases.build(base.system, 512, 128, 128, 30.0, name="max_sizes")
+    s = case.system
+    o = cases.oracle(case)
+    run(lib, case, "p64")
+    out = lib.cdwac_qp(s.n_states)
+    r = o.solve(0)
+    print(f"max sizes: QP {out[0]['qp']:.12f} (oracle {r[0]:.12f}), {out[0]['n_rounds']} passes")
+    assert out[0]["flags"] == r[3] == 0
+    assert abs(out[0]["qp"] - r[0]) <= 1e-9 * abs(r[0])
+    e = float(s.eps[s.state_idx[0]])
+    oms = np.array([[e - 0.2, e + 0.05, e + 0.3]])
+    sig = lib.cdwac_sigma(oms)[0]
+    for k in range(3):
+        ref = o.sigma(0, oms[0, k])
+        assert abs(sig[k] - ref) <= 1e-9 * (abs(ref) + abs(o.sigma_x[0])), (k, sig[k], ref)
+
+
 def test_new_entry_points_reject_bad_arguments(lib):
     """Status codes of the batch, G-energy, evGW and full-CD entry points
     (checked before any launch)."""
