@@ -268,7 +268,7 @@ int cdwac_qp_hedin(cdwac_ctx *ctx, const double *vxc, cdwac_state_out *out, doub
 int cdwac_sigma_cd(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm, int32_t state,
                    double omega, double *out, int32_t *n_res);
 
-/* Diagonal spectral function (Sec. 4): with the complex self-energy
+/* Diagonal spectral function (Sec. 5.5): with the complex self-energy
  * Sigma_n = Sigma^x + R_n - I_n (the imaginary part comes from the residue
  * term, i.e. from the Pade models at |eps_m - w| + i eta),
  *   A_n(w) = (1/pi) |Im[1 / (w - eps_n - Sigma_n(w) + v^xc_n)]|.

@@ -32,7 +32,19 @@ Readings of passages the paper leaves open:
   change with |f| < 0.1 Ha on both sides is bisected to 1e-12 Ha, candidates
   with |f| > 1e-8 Ha at the final midpoint (a jump across a pole, not a zero)
   are dropped, and the root with the largest Z (then the one nearest eps_n)
-  is kept.
+  is kept;
+* optionally (``quad_limit``) the integral term takes the a_m -> 0 limit
+  analytically: W_nm(i w') = w0 g(w') + [W_nm(i w') - w0 g(w')] with
+  g = Gamma^2 / (Gamma^2 + w'^2), w0 the residue term's own W at a_m = 0; the
+  first part is integrated in closed form, the remainder by the quadrature.
+
+Test infrastructure only: the tests, the package's smoke check and the
+benchmark's CPU baseline use it; the GPU path never does.  Every function is
+pinned by tests/test_oracle_pins.py or tests/test_oracle_mlp.py except one
+result, whose parity is unpinned: the G_dH W0 root with the plain quadrature
+(``solve_hedin`` without ``quad_limit``), which sits next to the state's own
+shifted G pole where the quadrature steps (with the limit it is pinned
+against the pole form).
 """
 from __future__ import annotations
 
@@ -95,8 +107,10 @@ def polarizability(o_ia: np.ndarray, eps: np.ndarray, n_occ: int, z: complex,
     z = complex(z)
     d = spin * (1.0 / (z - delta) - 1.0 / (z + delta))
     if z.real == 0.0:
-        d = d.real
-    return (o_ia * d[None, :]) @ o_ia.T
+        return (o_ia * d.real[None, :]) @ o_ia.T
+    # o_ia is real: the real and imaginary parts of the sum are each a real
+    # product (no complex copy of o_ia)
+    return (o_ia * d.real[None, :]) @ o_ia.T + 1j * ((o_ia * d.imag[None, :]) @ o_ia.T)
 
 
 def polarizability_entries(o_ia: np.ndarray, eps: np.ndarray, n_occ: int, z: complex,
@@ -269,7 +283,8 @@ def residue_term(omega: float, eps: np.ndarray, eps_f: float, eta: float,
 
 def spectral_function(omega: float, eps_n: float, sigma: complex, vxc: float) -> float:
     """A_nn(omega) = (1/pi) |Im[(omega - eps_n - Sigma_n(omega) + v^xc_n)^-1]|
-    (the diagonal spectral function of Sec. 4, normalised like a Lorentzian)."""
+    (the diagonal spectral function the paper discusses in Sec. 5.5, normalised
+    like a Lorentzian)."""
     return abs((1.0 / (omega - eps_n - sigma + vxc)).imag) / math.pi
 
 

@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kQpThreads) void k_sigma_eval(QpArgs A, int n_omega
     }
 }
 
-// Diagonal spectral function (Sec. 4): with Sigma_n = Sigma^x + R_n - I_n
+// Diagonal spectral function (Sec. 5.5): with Sigma_n = Sigma^x + R_n - I_n
 // complex (Im from the residue term; the integral term is real for eta -> 0),
 // A_n(w) = (1/pi) |Im[1 / (w - eps_n - Sigma_n(w) + v^xc_n)]|.
 __global__ __launch_bounds__(kQpThreads) void k_spectral_eval(QpArgs A, int n_omega,

@@ -1,8 +1,11 @@
-"""Writes the stored oracle results for the 600-orbital workload.
+"""Writes the stored oracle results of a synthetic workload: QP energies,
+sampled W and sampled Sigma.
 
 Calls only the FP64 oracle (``oracle/``) on the seeded synthetic input; the
 GPU tests compare against the JSON this writes.  Run from the repository
-root:  python tests/golden/make_golden.py
+root:
+    python tests/golden/make_golden.py                      (acene_nmo600, ~12 min on 8 cores)
+    python tests/golden/make_golden.py precision_naux5000   (~1.5 h on 8 cores, ~26 GB of memory)
 """
 import json
 import os
@@ -17,12 +20,9 @@ sys.path.insert(0, ROOT)
 from oracle import cdwac_ref as R  # noqa: E402
 from paper_2305_15955_amd import grids, synth  # noqa: E402
 
-NAME = "acene_nmo600"
-
-
-def main():
-    spec = synth.WORKLOADS[NAME]
-    s = synth.make_workload(NAME)
+def main(name="acene_nmo600"):
+    spec = synth.WORKLOADS[name]
+    s = synth.make_workload(name)
     freq, wts = grids.gauss_legendre_imag(spec["n_freq"])
     lo, hi = grids.windows(s.eps, s.state_idx, spec["window_ev"])
     nim = spec["n_pade"] // 2
@@ -44,15 +44,15 @@ def main():
         for d in (-0.2, 0.1, 0.3):
             om = float(s.eps[n] + d)
             sig.append((n, om, o.sigma(n, om)))
-    out = dict(workload=NAME, seed=spec["seed"], oracle_prepare_s=t_prep,
+    out = dict(workload=name, seed=spec["seed"], oracle_prepare_s=t_prep,
                qp=[r[0] for r in res], z=[r[1] for r in res], n_evals=[r[2] for r in res],
                flags=[r[3] for r in res], sigma_x=[float(x) for x in o.sigma_x],
                w_im=w_im, w_re=w_re, sigma=sig)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{NAME}_oracle.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path, "qp (eV):", [q * synth.HARTREE_EV for q in out["qp"]])
 
 
 if __name__ == "__main__":
-    main()
+    main(*sys.argv[1:2])

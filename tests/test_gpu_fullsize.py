@@ -193,13 +193,15 @@ def test_naux5000_against_stored_oracle(lib):
     mdl = np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                                "paper_2305_15955_amd", "seed_model.npz"))
     lib.cdwac_mlp_set_model(mdl["theta"], mdl["mu"], mdl["sd"], float(mdl["out_mu"]), float(mdl["out_sd"]))
-    for key, prec, rank_tol, mlp in (("b16x3 (stated configuration)", "b16x3", 0.0, False),
-                                     ("b16x3 + learned seed (benchmark)", "b16x3", 0.0, True),
-                                     ("f16 every node", "f16", 0.0, False),
-                                     ("f16 skeleton nodes", "f16", SKELETON_TOL["f16"], False)):
+    # the benchmark accepts a seed at |f| <= 0.1 meV; 1 meV (the bar) is shown too
+    for key, prec, rank_tol, accept in (("b16x3 (stated configuration)", "b16x3", 0.0, None),
+                                        ("b16x3 + learned seed (benchmark)", "b16x3", 0.0, 0.1 * MEV),
+                                        ("b16x3 + learned seed accepted at 1 meV", "b16x3", 0.0, MEV),
+                                        ("f16 every node", "f16", 0.0, None),
+                                        ("f16 skeleton nodes", "f16", SKELETON_TOL["f16"], None)):
         prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi,
-                                    pade_tol=1e-9, prec=prec, freq_rank_tol=rank_tol, use_mlp_seed=mlp,
-                                    mlp_accept=MEV)
+                                    pade_tol=1e-9, prec=prec, freq_rank_tol=rank_tol,
+                                    use_mlp_seed=accept is not None, mlp_accept=accept or 0.0)
         lib.cdwac_prepare(sysc, prm)
         out = lib.cdwac_qp(s.n_states)
         d = np.array([(out[n]["qp"] - g["qp"][n]) / MEV for n in range(s.n_states)])
