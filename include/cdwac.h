@@ -263,8 +263,9 @@ int cdwac_qp_hedin(cdwac_ctx *ctx, const double *vxc, cdwac_state_out *out, doub
  * CD-WAC replaces.  state: index into sys->state_idx; the imaginary grid and
  * the precision come from prm (its Pade reference set is not used).
  * out: host [3] = {Sigma_n, R_n, I_n} (Ha).  n_res: host, the residue count
- * (may be NULL).  At most 256 residues per call.  Leaves the context
- * unprepared.  Synchronous. */
+ * (may be NULL).  The residues go through in chunks of at most 255 near-real
+ * planes per preparation (the imaginary-axis part is recomputed for each
+ * chunk).  Leaves the context unprepared.  Synchronous. */
 int cdwac_sigma_cd(cdwac_ctx *ctx, const cdwac_system *sys, const cdwac_params *prm, int32_t state,
                    double omega, double *out, int32_t *n_res);
 

@@ -1443,49 +1443,65 @@ int cdwac_sigma_cd(cdwac_ctx* ctx, const cdwac_system* sys, const cdwac_params* 
         rx.push_back(0.0);
     }
     const int nr = (int)rm.size();
-    // with the analytic limit one more point, i eta (a_m = 0), gives every
-    // m's W at the residue point of a_m = 0 directly
-    const int n_pts_re = nr + (prm->quad_limit ? 1 : 0);
-    if (n_pts_re > kMaxPade)
-        return fail(ctx, CDWAC_EINVAL, "%d residues exceed the %d near-real planes of one call", nr, kMaxPade);
-    if (prm->quad_limit) rx.push_back(0.0);
     if (n_res) *n_res = rf[0] == 0.0 && nr == 1 ? 0 : nr;
-    // one state; the residues are the near-real points (eta_ref = eta); every m fitted
-    cdwac_system s1 = *sys;
-    s1.n_states = 1;
-    s1.state_idx = sys->state_idx + state;
-    s1.o_nm = sys->o_nm + (size_t)state * sys->n_aux * n_mo;
-    s1.vxc = sys->vxc ? sys->vxc + state : nullptr;
-    s1.eps_fermi = ef;
-    cdwac_params p1 = *prm;
-    p1.n_ref_im = 0;
-    p1.ref_im_idx = nullptr;
-    p1.n_ref_re = n_pts_re;
-    p1.ref_re = rx.data();
-    p1.eta_ref = prm->eta > 0.0 ? prm->eta : 1e-3;
-    p1.win_lo = prm->win_lo + state;
-    p1.win_hi = prm->win_hi + state;
-    p1.use_mlp_seed = 0;
-    p1.fit_all = 1;
-    const int rc = prepare_impl(ctx, &s1, &p1, true);
-    ctx->prepared = false;             // a residue set, not a CD-WAC model
-    if (rc != CDWAC_OK) return rc;
+    // One preparation holds at most kMaxPade near-real planes, so the residues
+    // go through in chunks of kMaxPade - 1; the first chunk also carries the
+    // point i eta (a_m = 0) of the analytic limit and gives I_n and Sigma^x,
+    // every chunk its share of R_n.  The imaginary-axis part is computed
+    // again for each chunk.
+    const int per = kMaxPade - 1;
     hipStream_t st = ctx->stream;
-    const size_t o_rm = 0, o_rf = (sizeof(int) * nr + 255) / 256 * 256, o_out = o_rf + (sizeof(double) * nr + 255) / 256 * 256;
-    TRY(ensure_batch(ctx, o_out + 256));
-    char* base = (char*)ctx->batch;
-    TRY(upload(ctx, (int*)(base + o_rm), rm.data(), nr));
-    TRY(upload(ctx, (double*)(base + o_rf), rf.data(), nr));
-    const Plan& P = ctx->plan;
-    if (prm->quad_limit) {
-        launch_w0_from_points(st, P.n_fit, at<double>(ctx, P.w_re), n_pts_re, nr, at<double>(ctx, P.w0));
+    const size_t o_rm = 0, o_rf = (sizeof(int) * per + 255) / 256 * 256,
+                 o_out = o_rf + (sizeof(double) * per + 255) / 256 * 256;
+    double first[3] = {0.0, 0.0, 0.0}, r_rest = 0.0;
+    for (int c0 = 0; c0 < nr; c0 += per) {
+        const int cn = std::min(per, nr - c0);
+        const bool lim = c0 == 0 && prm->quad_limit;
+        const int n_pts_re = cn + (lim ? 1 : 0);
+        std::vector<double> px(rx.begin() + c0, rx.begin() + c0 + cn);
+        if (lim) px.push_back(0.0);
+        // one state; the residues are the near-real points (eta_ref = eta); every m fitted
+        cdwac_system s1 = *sys;
+        s1.n_states = 1;
+        s1.state_idx = sys->state_idx + state;
+        s1.o_nm = sys->o_nm + (size_t)state * sys->n_aux * n_mo;
+        s1.vxc = sys->vxc ? sys->vxc + state : nullptr;
+        s1.eps_fermi = ef;
+        cdwac_params p1 = *prm;
+        p1.n_ref_im = 0;
+        p1.ref_im_idx = nullptr;
+        p1.n_ref_re = n_pts_re;
+        p1.ref_re = px.data();
+        p1.eta_ref = prm->eta > 0.0 ? prm->eta : 1e-3;
+        p1.win_lo = prm->win_lo + state;
+        p1.win_hi = prm->win_hi + state;
+        p1.use_mlp_seed = 0;
+        p1.fit_all = 1;
+        p1.quad_limit = lim ? 1 : 0;      // I_n is taken from the first chunk only
+        const int rc = prepare_impl(ctx, &s1, &p1, true);
+        ctx->prepared = false;             // a residue set, not a CD-WAC model
+        if (rc != CDWAC_OK) return rc;
+        TRY(ensure_batch(ctx, o_out + 256));
+        char* base = (char*)ctx->batch;
+        TRY(upload(ctx, (int*)(base + o_rm), rm.data() + c0, cn));
+        TRY(upload(ctx, (double*)(base + o_rf), rf.data() + c0, cn));
+        const Plan& P = ctx->plan;
+        if (lim) {
+            launch_w0_from_points(st, P.n_fit, at<double>(ctx, P.w_re), n_pts_re, cn, at<double>(ctx, P.w0));
+            LAUNCHCK();
+        }
+        launch_sigma_direct(st, qp_args(ctx), omega, at<double>(ctx, P.w_re), n_pts_re, cn,
+                            (const int*)(base + o_rm), (const double*)(base + o_rf), (double*)(base + o_out));
         LAUNCHCK();
+        double part[3];
+        HIPCK(hipMemcpyAsync(part, base + o_out, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+        HIPCK(hipStreamSynchronize(st));
+        if (c0 == 0) std::copy(part, part + 3, first);
+        else r_rest += part[1];
     }
-    launch_sigma_direct(st, qp_args(ctx), omega, at<double>(ctx, P.w_re), n_pts_re, nr, (const int*)(base + o_rm),
-                        (const double*)(base + o_rf), (double*)(base + o_out));
-    LAUNCHCK();
-    HIPCK(hipMemcpyAsync(out, base + o_out, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
+    out[0] = first[0] + r_rest;
+    out[1] = first[1] + r_rest;
+    out[2] = first[2];
     return CDWAC_OK;
 }
 

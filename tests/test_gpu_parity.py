@@ -508,6 +508,27 @@ def test_maximum_grid_and_reference_sizes(lib):
         assert abs(sig[k] - ref) <= 1e-9 * (abs(ref) + abs(o.sigma_x[0])), (k, sig[k], ref)
 
 
+@pytest.mark.parametrize("quad_limit", [False, True])
+def test_full_cd_beyond_one_preparation_of_residues(lib, quad_limit):
+    """More residues than one preparation's near-real planes (301 occupied
+    orbitals above the core: chunks of 255 and 46): full-CD Sigma against
+    the oracle's full CD, 1e-9 of |Sigma^x| + |Sigma|, with and without the
+    analytic limit."""
+    n_mo, n_occ, n_aux = 330, 301, 48
+    s = synth.make_system(n_mo, n_occ, n_aux, 1, math.sqrt(synth.SCREENING / (n_occ * (n_mo - n_occ))), seed=77)
+    case = cases.build(s, 32, 8, 8, 30.0, name="many_residues")
+    full = R.FullCdOracle(s, case.freq, case.weight, case.lo, case.hi, eta=case.eta, quad_limit=quad_limit)
+    sysc, keep = lib.make_system(s)
+    prm, arrs = lib.make_params(case.freq, case.weight, case.ref_im, case.ref_re, case.lo, case.hi, eta=case.eta,
+                                prec="p64", quad_limit=quad_limit)
+    for om in (float(s.eps[0]) - 0.1, float(s.eps[0]) + 0.05):
+        got, r_term, i_term, n_res = lib.cdwac_sigma_cd(sysc, prm, 0, om)
+        ref = full.sigma(0, om)
+        print(f"{n_res} residues: Sigma {got:.12f} (oracle {ref:.12f})")
+        assert n_res > 255
+        assert abs(got - ref) <= 1e-9 * (abs(ref) + abs(full.sigma_x[0])), (om, got, ref)
+
+
 def test_new_entry_points_reject_bad_arguments(lib):
     """Status codes of the batch, G-energy, evGW and full-CD entry points
     (checked before any launch)."""
