@@ -231,11 +231,23 @@ def scaling(sizes, cd_qp_max):
         t = time.perf_counter()
         lib.cdwac_sigma_cd(sysc, prm1, 0, qp)
         t_res = time.perf_counter() - t
+        # the spectral function on 1000 points of the window from the prepared
+        # tables (Sec. 5.5): per point against one full-CD self-energy
+        lib.cdwac_solve(sysc, prm)
+        om_sp = (s.eps[0] + np.linspace(-25.0, 25.0, 1000) / synth.HARTREE_EV)[None, :]
+        lib.cdwac_spectral(om_sp)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lib.cdwac_spectral(om_sp)
+        torch.cuda.synchronize()
+        t_spec = time.perf_counter() - t
         row = {"n_mo": n_mo, "n_aux": n_aux, "n_occ": n_occ, "K": k, "cdwac_s": t_wac,
                "sigma_evals": out["n_evals"], "cd_residues": n_res, "cd_residue_part_s": t_res,
                "cd_imag_part_s": max(t_call - t_res, 0.0),
                "cd_qp_estimate_s": max(t_call - t_res, 0.0) + out["n_evals"] * t_res}
         row["cd_over_cdwac"] = row["cd_qp_estimate_s"] / t_wac
+        row["spectral_1000pts_s"] = t_spec
+        row["spectral_speedup_per_point"] = t_call / (t_spec / 1000.0)
         if n_mo <= cd_qp_max:
             e_n = float(s.eps[0])
             n_cd = [0]
