@@ -281,13 +281,13 @@ __device__ void qp_state(const QpArgs& A, int s, Shared& sh, QpOut* dst) {
         return true;
     };
     if (A.use_mlp && lo <= e_n + kSeedOffset[0] && e_n + kSeedOffset[3] <= hi) {
-        // learned seed: round 1 evaluates Sigma^c at four fixed offsets from
+        // learned seed: pass 1 evaluates Sigma^c at four fixed offsets from
         // eps_n; the zero w_C of the cubic through the four values of f is
         // the base estimate, and the network predicts the remaining
         // correction w* - w_C from eps_n, eps_F, Sigma^x - v^xc, the four
-        // Sigma^c values and w_C - eps_n.  Round 2 evaluates f at the seed and at seed +- h:
+        // Sigma^c values and w_C - eps_n.  Pass 2 evaluates f at the seed and at seed +- h:
         // the seed is the root if |f| <= mlp_accept and Z is in (0, 1].  Else,
-        // with a physical Z, round 3 takes one Newton step with that slope and
+        // with a physical Z, pass 3 takes one Newton step with that slope and
         // applies the same test to its point.
         double xs[4], fs[4];
 #pragma unroll

@@ -251,12 +251,12 @@ def test_thiele_greedy_order_by_hand():
     assert t2(-9.0) == pytest.approx((9.0 - 24.0j) / 73.0, abs=1e-15)
     assert 1.0 / w[1] == pytest.approx(1.0 + 1.0j)
     l1 = lambda r: np.abs(r.real) + np.abs(r.imag)
-    # round 2 (T = W_0 = 1): L1 picks 1, the modulus would pick 2, the minimum 3
+    # step 2 (T = W_0 = 1): L1 picks 1, the modulus would pick 2, the minimum 3
     rest = [1, 2, 3, 4, 5]
     r = w[rest] - 1.0
     assert rest[int(np.argmax(l1(r)))] == 1
     assert rest[int(np.argmax(np.abs(r)))] == 2 and rest[int(np.argmin(l1(r)))] == 3
-    # round 3 (T = t2): L1 picks 5, the modulus 2; an un-updated T = 1 would pick 2
+    # step 3 (T = t2): L1 picks 5, the modulus 2; an un-updated T = 1 would pick 2
     rest = [2, 3, 4, 5]
     r = w[rest] - t2(u[rest])
     assert rest[int(np.argmax(l1(r)))] == 5
