@@ -529,6 +529,28 @@ def test_full_cd_beyond_one_preparation_of_residues(lib, quad_limit):
         assert abs(got - ref) <= 1e-9 * (abs(ref) + abs(full.sigma_x[0])), (om, got, ref)
 
 
+def test_spectral_function_with_quad_limit_fp64(lib):
+    """The spectral function with the analytic a_m -> 0 limit of the integral
+    term: complex Sigma next to eps_n (where the limit matters) and across
+    the window against the oracle with the same limit, 1e-9 of |Sigma^x| +
+    |Sigma|, and A_n to the bound that follows from it."""
+    case = cases.workload("fp64_1core_nmo60")
+    s = case.system
+    o = cases.oracle(case, fit_all=True, quad_limit=True)
+    run(lib, case, "p64", fit_all=True, quad_limit=True)
+    e = float(s.eps[s.state_idx[0]])
+    oms = np.array([[e - 0.3, e - 1e-4, e + 1e-4, e + 0.05, e + 0.3]])
+    spec, sre, sim = lib.cdwac_spectral(oms, parts=True)
+    for k in range(oms.shape[1]):
+        w = float(oms[0, k])
+        sig = o.sigma_complex(0, w)
+        ds = 1e-9 * (abs(sig) + abs(o.sigma_x[0]))
+        assert abs(sre[0, k] - sig.real) <= ds and abs(sim[0, k] - sig.imag) <= ds, (k, sre[0, k], sim[0, k], sig)
+        a_ref = o.spectral(0, w)
+        d = abs(w - e - sig + o.vxc[0])
+        assert abs(spec[0, k] - a_ref) <= a_ref * ds * (1.0 / max(abs(sig.imag), ds) + 2.0 / d) + 1e-300, k
+
+
 def test_new_entry_points_reject_bad_arguments(lib):
     """Status codes of the batch, G-energy, evGW and full-CD entry points
     (checked before any launch)."""
@@ -769,7 +791,7 @@ def sigma_sensitivity(case, o, oms, rel=1e-13, trials=2, seed=1):
 
 @pytest.mark.parametrize("which", ["ragged", "fp64_1core_nmo60", "one_transition"])
 def test_spectral_function_fp64(lib, which):
-    """Diagonal spectral function (Sec. 4) on a dense grid through the whole
+    """Diagonal spectral function (Sec. 5.5) on a dense grid through the whole
     window.  The complex self-energy agrees to the conditioning bar of
     sigma_tolerance (far below eps_n the continuation amplifies last-digit
     differences of W by up to ~1e7).  A_n agrees to the accuracy that follows:
