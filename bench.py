@@ -464,8 +464,8 @@ def main():
     nb = int(math.ceil(s.n_aux / 256.0))
     kpad = int(math.ceil(k_dim / 32.0) * 32)
     if args.prec == "p64":
-        nt = nb * 4
-        tile_elems = nt * (nt + 1) // 2 * 64 * 64
+        nt = nb * 2
+        tile_elems = nt * (nt + 1) // 2 * 128 * 128         # lower-triangle 128 x 128 FP64 tiles
     else:
         tile_elems = nb * (nb + 1) // 2 * 256 * 256        # lower-triangle 256 x 256 tiles
     issued = float(n_f) / n_launch * tile_elems * kpad * 2.0 * PRODUCTS[args.prec]
@@ -481,6 +481,17 @@ def main():
         # no single-kernel roofline
         res["roofline"] = None
     res["stages_ms"] = stages
+    # the W contraction stage against the same peak: C = Lambda B^T with
+    # 2 N_aux^2 flop per column, every (n, m) column at the imaginary planes
+    # and the fitted ones at the near-real planes (the stage also holds the
+    # small transposes of B, so this is a lower bound for its kernel)
+    _, _, _, (m0, m1) = lib.cdwac_w_table(s.n_states, s.n_mo, len(freq), len(ref_re))
+    n_fit = int(np.sum(m1 - m0))
+    flops_w = 2.0 * s.n_aux * s.n_aux * (n_im_planes * s.n_states * s.n_mo + (n_f - n_im_planes) * n_fit)
+    w_s = stages["w_contraction"] * 1e-3
+    res["roofline_w"] = {"bound": "mfma", "achieved": flops_w / w_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                         "frac": flops_w / w_s / 1e12 / peak, "kernel": "k_w_gemm (the whole W stage)",
+                         "algorithmic_flop_per_step": flops_w, "stage_ms": w_s * 1e3}
     # spectral function (Sec. 5.5) on 5000 points per state over a 50 eV range,
     # from the prepared tables of the last step
     om = np.stack([s.eps[s.state_idx[n]] + np.linspace(-25.0, 25.0, 5000) / synth.HARTREE_EV
@@ -512,8 +523,13 @@ def main():
     if args.fp64_steps > 0 and args.prec != "p64":
         out64, dt64, st64, _ = run_steps("p64", False, args.fp64_warmup, args.fp64_steps)
         err = [abs(a["qp"] - b["qp"]) * synth.HARTREE_EV * 1e3 for a, b in zip(out, out64)]
+        pi64_s = st64["polarizability"] * 1e-3            # one k_pi_f64 launch over every plane
+        flops64 = float(n_f) * s.n_aux * (s.n_aux + 1) * k_dim
         res["fp64_path"] = {"value": s.n_states / dt64, "ms_per_step": dt64 * 1e3, "steps": args.fp64_steps,
                             "warmup": args.fp64_warmup, "stages_ms": st64,
+                            "roofline": {"bound": "mfma", "kernel": "k_pi_f64", "achieved": flops64 / pi64_s / 1e12,
+                                         "peak": PEAK["p64"] / 1e12, "unit": "TFLOP/s",
+                                         "frac": flops64 / pi64_s / PEAK["p64"], "launch_ms": pi64_s * 1e3},
                             "n_evals_mean": float(np.mean([o["n_evals"] for o in out64])),
                             "n_rounds_mean": float(np.mean([o["n_rounds"] for o in out64]))}
         res["mev_err_vs_fp64"] = {"max": max(err), "mean": float(np.mean(err)), "per_state": err}
