@@ -20,7 +20,9 @@ roots by up to 3.9 meV (158-orbital system); with 24 points by at most
 ~1e-4 (RPA poles of ~10 Ha within eta_ref = 1e-3 of the points); with those
 planes on the FP64 path, W keeps <= 2e-7 of the state's largest value.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -200,6 +202,24 @@ def test_uneven_batch_48_systems(lib):
         assert not x["flags"] & R.FLAG_NOROOT and r[3] == 0 and 0.9 < x["z"] <= 1.0, (n, x, r)
         assert abs(x["qp"] - r[0]) <= MEV, (n, x["qp"], r[0])
     del sy, pr, kp
+    # every system whose oracle QP energies are stored (tests/golden/batch48_oracle.json,
+    # written by tests/golden/make_batch_golden.py from the smallest system up)
+    stored = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch48_oracle.json")
+    if os.path.exists(stored):
+        g = json.load(open(stored))
+        worst, n_cmp = 0.0, 0
+        for key, sy in g["systems"].items():
+            j = int(key)
+            assert sy["n_mo"] == specs[j]["n_mo"] and len(sy["qp"]) == len(res[j]), j
+            for n, x in enumerate(res[j]):
+                assert bool(x["flags"] & R.FLAG_NOROOT) == bool(sy["flags"][n] & R.FLAG_NOROOT), (j, n)
+                if not sy["flags"][n] & R.FLAG_NOROOT:
+                    err = abs(x["qp"] - sy["qp"][n])
+                    worst = max(worst, err)
+                    n_cmp += 1
+                    assert err <= MEV, (j, n, x["qp"], sy["qp"][n], err / MEV)
+        print(f"stored oracle values: {len(g['systems'])} systems, {n_cmp} states within "
+              f"{worst / MEV:.4f} meV", flush=True)
     for j in order[:5]:
         o = cases.oracle(cs[j])
         for n, r in enumerate(o.solve_all()):
