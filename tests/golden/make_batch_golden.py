@@ -5,7 +5,8 @@ N_mo, 1-12 core states) with 48 imaginary Gauss-Legendre nodes and 24 Pade
 points (12 imaginary, 12 near-real), the settings of the GPU batch test.
 Calls only the FP64 oracle (``oracle/``) on the seeded synthetic inputs; the
 systems go from the smallest to the largest, and the file is rewritten
-after each one ("complete" is set once all are there).  About 4 h on 8 host
+after each one ("complete" is set once all are there); a run started on an
+existing file with the same settings keeps its systems and adds the rest.  About 4 h on 8 host
 cores.  Run from the repository root:
     python tests/golden/make_batch_golden.py
 """
@@ -30,10 +31,18 @@ def main():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch48_oracle.json")
     out = dict(n_systems=len(specs), seed=400, n_freq=N_FREQ, n_pade=N_IM + N_RE, window_ev=WINDOW_EV,
                complete=False, systems={})
+    if os.path.exists(path):
+        # resume: the systems already written for the same settings are kept
+        # (each system's result depends on its own seeded input only)
+        old = json.load(open(path))
+        if all(old.get(k) == out[k] for k in ("n_systems", "seed", "n_freq", "n_pade", "window_ev")):
+            out["systems"] = old["systems"]
     freq, wts = grids.gauss_legendre_imag(N_FREQ)
     for j in np.argsort([sp["n_mo"] for sp in specs], kind="stable"):
         j = int(j)
         sp = specs[j]
+        if str(j) in out["systems"]:
+            continue
         t = time.time()
         s = synth.make_system(sp["n_mo"], sp["n_occ"], sp["n_aux"], sp["n_core"], sp["sigma"], seed=sp["seed"])
         lo, hi = grids.windows(s.eps, s.state_idx, WINDOW_EV)
