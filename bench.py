@@ -537,13 +537,15 @@ def main():
         # no single-kernel roofline
         res["roofline"] = None
     res["stages_ms"] = stages
-    # the W contraction stage against the same peak: C = Lambda B^T with
-    # 2 N_aux^2 flop per column, every (n, m) column at the imaginary planes
-    # and the fitted ones at the near-real planes (the stage also holds the
-    # small transposes of B, so this is a lower bound for its kernel)
+    # the W contraction stage against the same peak: the quadratic form
+    # o^T Lambda o of a symmetric Lambda takes N_aux (N_aux + 1) / 2 products
+    # per column (its lower triangle), N_aux (N_aux + 1) flop, for every (n, m)
+    # column at the imaginary planes and the fitted ones at the near-real
+    # planes (the stage also holds the small transposes of B, so this is a
+    # lower bound for its kernel)
     _, _, _, (m0, m1) = lib.cdwac_w_table(s.n_states, s.n_mo, len(freq), len(ref_re))
     n_fit = int(np.sum(m1 - m0))
-    flops_w = 2.0 * s.n_aux * s.n_aux * (n_im_planes * s.n_states * s.n_mo + (n_f - n_im_planes) * n_fit)
+    flops_w = s.n_aux * (s.n_aux + 1.0) * (n_im_planes * s.n_states * s.n_mo + (n_f - n_im_planes) * n_fit)
     w_s = stages["w_contraction"] * 1e-3
     res["roofline_w"] = {"bound": "mfma", "achieved": flops_w / w_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                          "frac": flops_w / w_s / 1e12 / peak, "kernel": "k_w_gemm (the whole W stage)",

@@ -88,9 +88,11 @@ __device__ inline void f64_store(F64Stage& st, const F64Frag& fr, int row, int k
     }
 }
 
-// acc = A[128 rows] * (B[128 rows] * diag(cw))^T over K (a multiple of 16).
+// acc = A[128 rows] * (B[128 rows] * diag(cw))^T over the first K columns (a
+// multiple of 16); the partial sum over the first 16 n_dbl columns is doubled
+// before the rest is added (n_dbl < 0: never).
 __device__ inline void f64_tile_product(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-                                         int64_t ldb, const double* __restrict__ cw, int64_t K,
+                                         int64_t ldb, const double* __restrict__ cw, int64_t K, int64_t n_dbl,
                                          F64Stage (&st)[2], v4d (&acc)[4][4]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = w >> 1, wc = w & 1;
@@ -106,6 +108,11 @@ __device__ inline void f64_tile_product(const double* __restrict__ A, int64_t ld
     for (int64_t i = 0; i < nk; ++i) {
         const int s = (int)(i & 1);
         if (i + 1 < nk) f64_load(fr, arow, brow, crow, (i + 1) * F_KC);
+        if (i == n_dbl)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] *= 2.0;
         f64_chunk(st[s], wr, wc, lane, acc);
         if (i + 1 < nk) f64_store(st[s ^ 1], fr, row, kq);
         __syncthreads();
@@ -134,7 +141,7 @@ __global__ __launch_bounds__(256, 2) void k_pi_f64(const double* __restrict__ x,
     lower_tile(bid % T, I, J);
     v4d acc[4][4] = {};
     f64_tile_product(x + (int64_t)I * F_BT * kpad, kpad, x + (int64_t)J * F_BT * kpad, kpad,
-                      cw + (int64_t)f * kpad, kpad, st, acc);
+                      cw + (int64_t)f * kpad, kpad, -1, st, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
     const double id = idflag[f] ? 1.0 : 0.0;
     double* Ef = E + (int64_t)f * npad * npad;
@@ -150,8 +157,12 @@ __global__ __launch_bounds__(256, 2) void k_pi_f64(const double* __restrict__ x,
             }
 }
 
-// partial[f][I][c] = sum_{P in tile I} B[c][P] (Lambda_f B^T)[P][c], FP64,
-// 128 x 128 tiles (npad and cpad multiples of 128).
+// partial[f][I][c] = sum_{P in tile I} B[c][P] (Lambda'_f B^T)[P][c], FP64,
+// 128 x 128 tiles (npad and cpad multiples of 128), where Lambda' keeps the
+// 128-row blocks of Lambda left of and on its diagonal only, the ones left of
+// it doubled: Lambda is symmetric, so the partials of all row blocks still sum
+// to the full quadratic form B[c] Lambda B[c]^T (Eq. wriv) at about half the
+// products.  Row blocks go from the last (the longest contraction) down.
 __global__ __launch_bounds__(256, 2) void k_w_f64(const double* __restrict__ lam, int npad,
                                                   const double* __restrict__ bt, int cpad,
                                                   int f0, double* __restrict__ partial) {
@@ -161,11 +172,11 @@ __global__ __launch_bounds__(256, 2) void k_w_f64(const double* __restrict__ lam
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int fl = bid / (ni * nc);
     const int rem = bid % (ni * nc);
-    const int I = rem % ni, J = rem / ni;
+    const int I = ni - 1 - rem % ni, J = rem / ni;
     const double* L = lam + (int64_t)(f0 + fl) * npad * npad;
     v4d acc[4][4] = {};
     f64_tile_product(L + (int64_t)I * F_BT * npad, npad, bt + (int64_t)J * F_BT * npad, npad,
-                      nullptr, npad, st, acc);
+                      nullptr, (int64_t)(I + 1) * F_BT, (int64_t)I * (F_BT / F_KC), st, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
@@ -293,16 +304,17 @@ __device__ inline void gemm_chunk(const uint4* lds, int st, int r0, int c0, int 
     }
 }
 
-// acc = A[rows 0..256) * B[rows 0..256)^T over K (multiple of RG::GK); A and
-// B point at the first row block of the tile.  Wave w owns rows
+// acc = A[rows 0..256) * B[rows 0..256)^T over the first nk chunks of RG::GK
+// columns of K (the panels' K extent, a multiple of RG::GK); A and B point at
+// the first row block of the tile.  The partial sum over the first n_dbl chunks
+// is doubled before the rest is added (n_dbl < 0: never).  Wave w owns rows
 // 64 (w / 2) .. +64 and columns 128 (w % 2) .. +128.
 template <int ET, bool SPLIT, class RG>
 __device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, const uint16_t* __restrict__ al,
                                  const uint16_t* __restrict__ bh, const uint16_t* __restrict__ bl, int64_t K,
-                                 v16f (&acc)[2][4]) {
+                                 int64_t nk, int64_t n_dbl, v16f (&acc)[2][4]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int r0 = (w >> 1) * 64, c0 = (w & 1) * 128;
-    const int64_t nk = K / RG::GK;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -321,6 +333,11 @@ __device__ inline void gemm_tile(uint4* lds, const uint16_t* __restrict__ ah, co
         if (i + NST - 1 < nk)
             gemm_issue<SPLIT, RG>(lds, (int)((i + NST - 1) % NST), ah, al, bh, bl, K, (i + NST - 1) * RG::GK, w,
                                   lane);
+        if (i == n_dbl)
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] *= 2.0f;
         gemm_chunk<ET, SPLIT, RG>(lds, (int)(i % NST), r0, c0, lane, acc);
     }
 }
@@ -358,7 +375,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
     const int64_t ao = (int64_t)I * GT * kpad;
     const int64_t bo = (int64_t)fb * npad * kpad + (int64_t)J * GT * kpad;
     v16f acc[2][4];
-    gemm_tile<ET, SPLIT, PiRing<SPLIT>>(lds, xh + ao, xl + ao, yh + bo, yl + bo, kpad, acc);
+    gemm_tile<ET, SPLIT, PiRing<SPLIT>>(lds, xh + ao, xl + ao, yh + bo, yl + bo, kpad, kpad / PiRing<SPLIT>::GK, -1,
+                                        acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const double id = idflag[f] ? 1.0 : 0.0;
     const double us = pi_unscale[f];
@@ -379,7 +397,10 @@ __global__ __launch_bounds__(kGemmThreads) void k_pi_gemm(const uint16_t* __rest
 template <bool SPLIT>
 using WRing = Ring<SPLIT, 32, 8192>;
 
-// partial[fl][I][c] = sum_{P in row block I} B[c][P] (Lambda_f B^T)[P][c]
+// partial[fl][I][c] = sum_{P in row block I} B[c][P] (Lambda'_f B^T)[P][c],
+// where Lambda' keeps the 256-row blocks of Lambda left of and on its diagonal
+// only, the ones left of it doubled (as in k_w_f64): the partials of all row
+// blocks sum to B[c] Lambda_f B[c]^T (Eq. wriv) at about half the products.
 template <int ET, bool SPLIT>
 __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restrict__ lh,
                                                          const uint16_t* __restrict__ ll, int npad,
@@ -398,7 +419,9 @@ __global__ __launch_bounds__(kGemmThreads) void k_w_gemm(const uint16_t* __restr
     const int64_t lo = (int64_t)(f0 + fl) * npad * npad + (int64_t)I * GT * npad;
     const int64_t bo = (int64_t)J * GT * npad;
     v16f acc[2][4];
-    gemm_tile<ET, SPLIT, WRing<SPLIT>>(lds, lh + lo, ll + lo, bh + bo, bl + bo, npad, acc);
+    gemm_tile<ET, SPLIT, WRing<SPLIT>>(lds, lh + lo, ll + lo, bh + bo, bl + bo, npad,
+                                       (int64_t)(I + 1) * (GT / WRing<SPLIT>::GK), (int64_t)I * (GT / WRing<SPLIT>::GK),
+                                       acc);
     // the column sums reuse the ring once every wave is done reading it
     __syncthreads();
     double (*red)[GT] = reinterpret_cast<double (*)[GT]>(lds);
@@ -502,13 +525,15 @@ std::vector<int2> pi_worklist(int npad, int nfb, int cu_per_xcd) {
     return out;
 }
 
-// Full ni x nc grid of W tiles in 4 x 8 blocks.
+// Full ni x nc grid of W tiles in 4 x 8 blocks, from the last row block (the
+// longest contraction, I + 1 chunks of 256) down, so that a launch ends on the
+// short ones.
 std::vector<int2> w_tiles(int npad, int cpad) {
     std::vector<int2> out;
     const int nI = npad / GT, nJ = cpad / GT;
-    for (int I0 = 0; I0 < nI; I0 += 4)
+    for (int I1 = nI; I1 > 0; I1 -= 4)
         for (int J0 = 0; J0 < nJ; J0 += 8)
-            for (int I = I0; I < std::min(nI, I0 + 4); ++I)
+            for (int I = I1 - 1; I >= std::max(0, I1 - 4); --I)
                 for (int J = J0; J < std::min(nJ, J0 + 8); ++J) out.push_back(make_int2(I, J));
     return out;
 }
