@@ -53,6 +53,29 @@ int main() {
                 }
             }
     if (cdwac::pi_batch_size(48, 16, 210, 256) != 12) ++bad;
+    // W tiles: every (row block I, column block J) of the grid exactly once,
+    // row blocks from the last down (the contraction over Lambda's lower block
+    // triangle makes row block I cost I + 1 chunks of 256)
+    for (int npad : {256, 512, 1280, 5120, 6656})
+        for (int cpad : {256, 768, 24064}) {
+            const std::vector<int2> t = cdwac::w_tiles(npad, cpad);
+            const int nI = npad / 256, nJ = cpad / 256;
+            std::set<long> seen;
+            int last_band = 0;
+            for (const int2 e : t) {
+                if (e.x < 0 || e.x >= nI || e.y < 0 || e.y >= nJ || !seen.insert((long)e.x * nJ + e.y).second) {
+                    ++bad;
+                    continue;
+                }
+                const int band = (nI - 1 - e.x) / 4;   // bands of 4 row blocks, counted from the last
+                if (band < last_band) ++bad;
+                last_band = band;
+            }
+            if ((long)seen.size() != (long)nI * nJ) {
+                ++bad;
+                std::printf("w_tiles npad %d cpad %d: %zu tiles\n", npad, cpad, seen.size());
+            }
+        }
     std::printf("%s\n", bad ? "FAIL" : "ok");
     return bad != 0;
 }
