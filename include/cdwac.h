@@ -320,7 +320,11 @@ int cdwac_inversion_residual(const cdwac_ctx *ctx, double *worst, int32_t *matri
  * allocation.  Limit: n_fit * n_pts <= 524288 (CDWAC_EINVAL beyond, checked
  * before any launch).  Every call on a device uses that device's one scratch
  * array: calls that overlap on one device (several contexts or host threads)
- * race and must be serialised by the caller.  Synchronous. */
+ * race and must be serialised by the caller.  Synchronous, except while the
+ * context's stream is being captured into a HIP graph: then the kernels and
+ * the copy of n_terms are recorded into the caller's graph and the call
+ * returns at once; the results appear when the graph runs (each replay reads
+ * u, w and x afresh and rewrites the scratch, out and n_terms). */
 int cdwac_pade_fit_eval_noalloc(cdwac_ctx *ctx, int32_t n_fit, int32_t n_pts, const double *u,
                                 const double *w, double tol, int32_t n_x, const double *x,
                                 double *out, int32_t *n_terms);

@@ -1755,7 +1755,11 @@ int cdwac_pade_fit_eval_noalloc(cdwac_ctx* ctx, int32_t n_fit, int32_t n_pts, co
     launch_thiele_eval(st, n_fit, n_pts, coef, node, nt, n_x, x, out);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && n_terms) e = hipMemcpyAsync(n_terms, nt, sizeof(int) * n_fit, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    // while the stream is being captured into a graph the launches and the
+    // copy are recorded, not run: the results appear when the graph runs
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (e == hipSuccess) e = hipStreamIsCapturing(st, &cap);
+    if (e == hipSuccess && cap == hipStreamCaptureStatusNone) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ctx, CDWAC_EHIP, "pade fit (fixed scratch): %s", hipGetErrorString(e));
     return CDWAC_OK;
 }

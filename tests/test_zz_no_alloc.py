@@ -2,7 +2,8 @@
 the allocating one (cdwac_pade_fit_eval), through the C ABI: the same greedy
 Thiele fits (Sec. 3.2; Eqs. pade, rec_eq) and values, term counts identical,
 on two calls in a row (the second smaller, so it runs over what the first
-left in the fixed scratch), and the size limit rejected before any launch."""
+left in the fixed scratch), the size limit rejected before any launch, and
+the call recorded into a HIP graph and replayed."""
 import numpy as np
 import pytest
 
@@ -58,3 +59,68 @@ def test_noalloc_rejects_sizes_beyond_the_scratch(lib):
     with pytest.raises(cdwac.CdwacError) as e:
         lib.cdwac_pade_fit_eval_noalloc(u, u, 1e-9, np.zeros((n_fit, 1), complex))
     assert e.value.code == cdwac.CDWAC_EINVAL
+
+
+def test_noalloc_under_graph_capture():
+    """Recorded into a HIP graph on its context's stream and replayed four
+    times over two input sets copied into the same device buffers between
+    the replays: every replay equals the allocating entry point's eager
+    result for that set bit for bit, with eager work on the same context
+    between the replays."""
+    import ctypes
+
+    import torch
+    from paper_2305_15955_amd import cdwac
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    s = torch.cuda.Stream()
+    lib = cdwac.Cdwac(0, stream=s)
+    try:
+        n_fit, n_pts = 600, 24
+        sets = [fit_sets(n_fit, n_pts, seed) for seed in (5, 6)]
+        refs = [lib.cdwac_pade_fit_eval(u, w, 1e-9, x) for u, w, x in sets]
+        assert not np.array_equal(refs[0][0], refs[1][0])
+
+        def c2(a):
+            a = np.asarray(a, np.complex128)
+            return torch.from_numpy(np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1)))
+
+        host = [[c2(a) for a in st] for st in sets]
+        nx = sets[0][2].shape[1]
+        dev = [t.to("cuda:0") for t in host[0]]
+        out = torch.empty((n_fit, nx, 2), dtype=torch.float64, device="cuda:0")
+        nt = torch.empty(n_fit, dtype=torch.int32, device="cuda:0")
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+
+        def call():
+            return lib.lib.cdwac_pade_fit_eval_noalloc(lib.ctx, n_fit, n_pts, p(dev[0]), p(dev[1]), 1e-9, nx,
+                                                       p(dev[2]), p(out), p(nt))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            assert call() == 0                      # eager, outside the capture
+        s.synchronize()
+        g = torch.cuda.CUDAGraph()
+        out.zero_()
+        torch.cuda.synchronize()
+        print("capturing the allocation-free fit call", flush=True)
+        with torch.cuda.graph(g, stream=s):
+            rc = call()
+        assert rc == 0, rc
+        for k in (0, 1, 0, 1):
+            print(f"replay with input set {k}", flush=True)
+            with torch.cuda.stream(s):
+                for d, h in zip(dev, host[k]):
+                    d.copy_(h.to("cuda:0"))
+                out.zero_()
+                nt.zero_()
+            s.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            np.testing.assert_array_equal(nt.cpu().numpy(), refs[k][1])
+            np.testing.assert_array_equal(o[..., 0] + 1j * o[..., 1], refs[k][0])
+            # eager work on the same context between the replays
+            again = lib.cdwac_pade_fit_eval(*sets[1 - k][:2], 1e-9, sets[1 - k][2])
+            np.testing.assert_array_equal(again[0], refs[1 - k][0])
+        del g
+    finally:
+        lib.close()
