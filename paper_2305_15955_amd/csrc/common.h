@@ -104,4 +104,31 @@ __device__ inline int xcd_remap(int bid, int nblocks) {
     return (bid % kXcd) * per + bid / kXcd;
 }
 
+// Tile t of the lower triangle of an n x n grid of blocks (J <= I), in the
+// order of the sweep's rank-k updates: bands of 4 block rows from the top,
+// each cut into pieces of 8 block columns, a piece's tiles row by row.  The
+// 32 tiles an XCD runs together then read 4 row panels and 8 column panels
+// instead of one row panel and 32 column panels, so that the column panels
+// are fetched from HBM about once per band instead of once per block row.
+__host__ __device__ inline void sweep_tile_order(int t, int n, int& I, int& J) {
+    // band b holds block rows 4b .. 4b + 3, starting at tile 4b (4b + 1) / 2
+    int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.125);   // 2b (4b + 1) <= t, up to rounding
+    while (b > 0 && 2 * b * (4 * b + 1) > t) --b;
+    while (2 * (b + 1) * (4 * (b + 1) + 1) <= t && 4 * (b + 1) < n) ++b;
+    int local = t - 2 * b * (4 * b + 1);
+    const int r1 = n - 4 * b < 4 ? n - 4 * b : 4;   // rows in the band
+    I = J = 0;   // not reached for 0 <= t < n (n + 1) / 2
+    for (int c = 0; 8 * c < n; ++c)
+        for (int r = 0; r < r1; ++r) {
+            const int row = 4 * b + r, cnt = row + 1 - 8 * c;
+            const int k = cnt < 0 ? 0 : (cnt > 8 ? 8 : cnt);
+            if (local < k) {
+                I = row;
+                J = 8 * c + local;
+                return;
+            }
+            local -= k;
+        }
+}
+
 }  // namespace cdwac

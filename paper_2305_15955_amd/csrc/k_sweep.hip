@@ -189,11 +189,8 @@ __global__ __launch_bounds__(256) void k_sweep_update(double* __restrict__ E, in
     const int nblk = npad / kNb, T = nblk * (nblk + 1) / 2;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int mat = bid / T;
-    const int t = bid % T;
-    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    while (I * (I + 1) / 2 > t) --I;
-    const int J = t - I * (I + 1) / 2;
+    int I, J;
+    sweep_tile_order(bid % T, nblk, I, J);
     constexpr int NK = KW / kNb;                 // pivot blocks of this step
     if ((I >= kb && I < kb + NK) || (J >= kb && J < kb + NK)) return;
     const int planes = C ? 2 : 1;

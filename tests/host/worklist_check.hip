@@ -76,6 +76,39 @@ int main() {
                 std::printf("w_tiles npad %d cpad %d: %zu tiles\n", npad, cpad, seen.size());
             }
         }
+    // tile order of the sweep's updates: every lower-triangle tile of an n x n
+    // block grid exactly once, bands of 4 block rows in order, every 32
+    // consecutive tiles of a full band within 4 row and 8 column blocks
+    for (int n = 1; n <= 256; ++n) {
+        const int T = n * (n + 1) / 2;
+        std::set<long> seen;
+        int last_band = 0;
+        std::vector<int> ti(T), tj(T);
+        for (int t = 0; t < T; ++t) {
+            int I = -1, J = -1;
+            cdwac::sweep_tile_order(t, n, I, J);
+            ti[t] = I;
+            tj[t] = J;
+            if (I < 0 || I >= n || J < 0 || J > I || !seen.insert((long)I * n + J).second || I / 4 < last_band) {
+                ++bad;
+                std::printf("sweep order n %d t %d -> (%d, %d)\n", n, t, I, J);
+                break;
+            }
+            last_band = I / 4;
+        }
+        if ((int)seen.size() != T) ++bad;
+        for (int t0 = 0; t0 + 32 <= T; t0 += 32) {
+            std::set<int> rows, cols;
+            for (int t = t0; t < t0 + 32; ++t) {
+                rows.insert(ti[t]);
+                cols.insert(tj[t]);
+            }
+            // a run inside one full band, away from its diagonal, touches 4 x 8 blocks
+            if (ti[t0] / 4 == ti[t0 + 31] / 4 && 4 * (ti[t0] / 4) + 3 < n && tj[t0 + 31] + 4 <= 4 * (ti[t0] / 4) &&
+                (rows.size() > 4 || cols.size() > 16))
+                ++bad;
+        }
+    }
     std::printf("%s\n", bad ? "FAIL" : "ok");
     return bad != 0;
 }
