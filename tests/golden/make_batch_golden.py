@@ -6,8 +6,8 @@ points (12 imaginary, 12 near-real), the settings of the GPU batch test.
 Calls only the FP64 oracle (``oracle/``) on the seeded synthetic inputs; the
 systems go from the smallest to the largest, and the file is rewritten
 after each one ("complete" is set once all are there); a run started on an
-existing file with the same settings keeps its systems and adds the rest.  About 4 h on 8 host
-cores.  Run from the repository root:
+existing file with the same settings keeps its systems and adds the rest.  About 8 h on 8 host
+cores (the largest systems take 20-40 min each).  Run from the repository root:
     python tests/golden/make_batch_golden.py
 """
 import json
