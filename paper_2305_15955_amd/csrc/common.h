@@ -106,10 +106,11 @@ __device__ inline int xcd_remap(int bid, int nblocks) {
 
 // Tile t of the lower triangle of an n x n grid of blocks (J <= I), in the
 // order of the sweep's rank-k updates: bands of 4 block rows from the top,
-// each cut into pieces of 8 block columns, a piece's tiles row by row.  The
-// 32 tiles an XCD runs together then read 4 row panels and 8 column panels
-// instead of one row panel and 32 column panels, so that the column panels
-// are fetched from HBM about once per band instead of once per block row.
+// each cut into pieces of 8 block columns, a piece's tiles row by row.  Every
+// 32 consecutive tiles (an XCD runs consecutive tiles together) then read 4
+// row panels and 8 column panels instead of one row panel and 32 column
+// panels, so that a band's column panels come from HBM about once per band
+// instead of once per block row.
 __host__ __device__ inline void sweep_tile_order(int t, int n, int& I, int& J) {
     // band b holds block rows 4b .. 4b + 3, starting at tile 4b (4b + 1) / 2
     int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.125);   // 2b (4b + 1) <= t, up to rounding
